@@ -1,0 +1,196 @@
+"""CPU oracle for FORA whole-graph SSPPR (Algorithms 1 and 2 of the paper,
+r_max by eqn:rmax), plus exact PPR references and the MLP reference.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark may import this package; the product path never does. It is
+independent of the HIP implementation (no shared code, constants or helpers);
+both take their inputs from ``synth``.
+
+The arithmetic lives in ``fora_oracle.c`` (plain single-threaded C, FP64);
+this module only marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fora_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc -O2 (single-threaded, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
+                               "-fno-fast-math", "-ffp-contract=off",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, u32, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
+    lib.oracle_philox4x32_10.argtypes = [P, P, P]
+    lib.oracle_philox_many.argtypes = [i64, P, P, P]
+    lib.oracle_validate.argtypes = [i32, i64, P, P]
+    lib.oracle_validate.restype = ctypes.c_int
+    lib.oracle_constants.argtypes = [i64, f64, f64, f64, f64, f64, P]
+    lib.oracle_push.argtypes = [i32, P, P, i32, f64, f64, P, P, i32, P, P, P, i64, P]
+    lib.oracle_push.restype = i32
+    lib.oracle_plan.argtypes = [i32, P, f64, P, P, P]
+    lib.oracle_plan.restype = i64
+    lib.oracle_walks.argtypes = [i32, P, P, u32, u32, u32, i64, P, P, P, P, P, P, P]
+    lib.oracle_topk.argtypes = [i32, P, i32, P, P]
+    lib.oracle_topk.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _csr(g):
+    rp = np.ascontiguousarray(g.rowptr, dtype=np.int32)
+    ci = np.ascontiguousarray(g.colidx, dtype=np.int32)
+    return rp, ci
+
+
+# --------------------------------------------------------------------------
+def philox(ctrs: np.ndarray, key) -> np.ndarray:
+    """Philox4x32-10 blocks for an array of 4-word counters."""
+    lib = _load()
+    c = np.ascontiguousarray(ctrs, dtype=np.uint32).reshape(-1, 4)
+    k = np.ascontiguousarray(key, dtype=np.uint32).reshape(2)
+    out = np.empty_like(c)
+    lib.oracle_philox_many(c.shape[0], _p(c), _p(k), _p(out))
+    return out
+
+
+def validate(g) -> int:
+    rp, ci = _csr(g)
+    return _load().oracle_validate(rp.shape[0] - 1, ci.shape[0], _p(rp), _p(ci))
+
+
+def constants(m: int, alpha: float, eps: float, delta: float, pf: float,
+              rmax: float | None = None) -> dict:
+    out = np.zeros(5, np.float64)
+    _load().oracle_constants(m, alpha, eps, delta, pf,
+                             0.0 if rmax is None else float(rmax), _p(out))
+    return dict(c=out[0], L=out[1], omega_unit=out[2], rmax=out[3],
+                t_alpha=int(out[4]))
+
+
+def push(g, s: int, alpha: float, rmax: float, max_rounds: int = 100000,
+         log_frontiers: bool = False, frontier_cap: int | None = None) -> dict:
+    """Synchronous Forward Push; returns r, q (FP64) and per-round data."""
+    lib = _load()
+    rp, ci = _csr(g)
+    n = rp.shape[0] - 1
+    r = np.zeros(n, np.float64)
+    q = np.zeros(n, np.float64)
+    sizes = np.zeros(max_rounds, np.int32)
+    ops = np.zeros(1, np.int64)
+    margin = np.zeros(1, np.float64)
+    cap = 0
+    flog = None
+    if log_frontiers:
+        cap = frontier_cap if frontier_cap is not None else 64 * n
+        flog = np.zeros(cap, np.int32)
+    rounds = lib.oracle_push(n, _p(rp), _p(ci), int(s), alpha, rmax, _p(r), _p(q),
+                             max_rounds, _p(sizes), _p(ops), _p(flog), cap,
+                             _p(margin))
+    if rounds < 0:
+        raise RuntimeError(f"oracle_push failed ({rounds})")
+    sizes = sizes[:rounds].copy()
+    out = dict(r=r, q=q, rounds=int(rounds), round_sizes=sizes,
+               edge_ops=int(ops[0]), min_margin=float(margin[0]))
+    if log_frontiers:
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        out["frontiers"] = [flog[offs[i]:offs[i + 1]].copy() for i in range(rounds)]
+    return out
+
+
+def plan(r: np.ndarray, omega_unit: float):
+    """Walk plan (v, omega_v, w_v) for v ascending with r(v) > 0."""
+    lib = _load()
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    n = r.shape[0]
+    pv = np.zeros(n, np.int32)
+    po = np.zeros(n, np.uint64)
+    pw = np.zeros(n, np.float64)
+    e = lib.oracle_plan(n, _p(r), omega_unit, _p(pv), _p(po), _p(pw))
+    if e < 0:
+        raise OverflowError("a per-node walk count does not fit in 32 bits")
+    return pv[:e].copy(), po[:e].copy(), pw[:e].copy()
+
+
+def walks(g, source: int, seed: int, t_alpha: int, plan_v, plan_omega, plan_w,
+          endpoints: bool = False) -> dict:
+    """Run every planned walk; endpoint counts, weighted sums and step total."""
+    lib = _load()
+    rp, ci = _csr(g)
+    n = rp.shape[0] - 1
+    pv = np.ascontiguousarray(plan_v, dtype=np.int32)
+    po = np.ascontiguousarray(plan_omega, dtype=np.uint64)
+    pw = np.ascontiguousarray(plan_w, dtype=np.float64)
+    cnt = np.zeros(n, np.uint64)
+    acc = np.zeros(n, np.float64)
+    steps = np.zeros(1, np.uint64)
+    W = int(po.sum())
+    ends = np.zeros(W, np.int32) if endpoints else None
+    lib.oracle_walks(n, _p(rp), _p(ci), source & 0xFFFFFFFF, seed & 0xFFFFFFFF,
+                     t_alpha, pv.shape[0], _p(pv), _p(po), _p(pw), _p(cnt),
+                     _p(acc), _p(steps), _p(ends))
+    out = dict(cnt=cnt, acc=acc, steps=int(steps[0]), walks=W)
+    if endpoints:
+        out["endpoints"] = ends
+    return out
+
+
+def topk(pi: np.ndarray, k: int):
+    lib = _load()
+    pi = np.ascontiguousarray(pi, dtype=np.float64)
+    ids = np.zeros(k, np.int32)
+    vals = np.zeros(k, np.float64)
+    rc = lib.oracle_topk(pi.shape[0], _p(pi), k, _p(ids), _p(vals))
+    if rc != 0:
+        raise ValueError("bad k")
+    return ids, vals
+
+
+def fora(g, s: int, alpha: float = 0.2, eps: float = 0.5, delta: float | None = None,
+         pf: float | None = None, k: int = 500, seed: int = 0,
+         rmax: float | None = None, log_frontiers: bool = False) -> dict:
+    """Whole-graph FORA (Algorithm 2) followed by top-k selection."""
+    n = g.n
+    delta = 1.0 / n if delta is None else delta
+    pf = 1.0 / n if pf is None else pf
+    if validate(g) != 0:
+        raise ValueError("invalid graph")
+    c = constants(g.m, alpha, eps, delta, pf, rmax)
+    ps = push(g, s, alpha, c["rmax"], log_frontiers=log_frontiers)
+    pv, po, pw = plan(ps["r"], c["omega_unit"])
+    wk = walks(g, s, seed, c["t_alpha"], pv, po, pw)
+    pi = ps["q"] + wk["acc"]
+    ids, vals = topk(pi, min(k, n))
+    out = dict(consts=c, plan=(pv, po, pw), pi=pi, topk_ids=ids, topk_vals=vals,
+               r_sum=float(ps["r"].sum()))
+    out.update(ps)
+    out.update(wk)
+    return out
