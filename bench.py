@@ -1,0 +1,160 @@
+"""Benchmark: FORA whole-graph SSPPR + top-500 on one MI355X.
+
+Workload (default): R-MAT, 2^20 nodes, 16 * 2^20 samples (a, b, c) =
+(.57, .19, .19), duplicates and self-loops removed, dangling nodes given one
+random out-edge; 100 seeded sources uniform over nodes with R-MAT out-degree
+>= 1; alpha = 0.2, eps = 0.5, delta = p_f = 1/n, k = 500.
+
+One step = the whole hot path (push, walk plan, walks, estimate, top-k) for
+all 100 sources in one batched call. The plain single-query loop over the
+same sources is timed beside it. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "walk-steps/s + SSPPR queries/s (eps=0.5, top-500) vs plain FORA, same GPU"
+PEAK_HBM_GBS = 8000.0
+# algorithmic bytes: per walk move 8 B node record + 4 B target id; per walk
+# 8 B plan read (amortised) + 4 B count + 8 B weight at the end point
+BYTES_PER_STEP = 12
+BYTES_PER_WALK = 20
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(g, src, alpha, eps, k, seed):
+    import oracle
+    t0 = time.perf_counter()
+    out = oracle.fora(g, int(src), alpha=alpha, eps=eps, k=k, seed=seed)
+    dt = time.perf_counter() - t0
+    return dict(value=out["steps"] / dt, unit="walk-steps/s", cores=1, kind="oracle",
+                queries_per_s=1.0 / dt, seconds=dt,
+                sample=f"1 source (node {int(src)}) of the workload, full query, "
+                       f"{out['steps']} walk steps, single-threaded FP64 C oracle")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat20")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-single", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1908_10583_amd import fora
+
+    alpha, eps, k, seed = 0.2, 0.5, 500, 0
+    t0 = time.perf_counter()
+    g, srcs = synth.workload(args.workload)
+    log(f"graph {g.name}: n={g.n} m={g.m} sources={len(srcs)} ({time.perf_counter()-t0:.1f}s)")
+    G = fora.Graph.from_numpy(g.rowptr, g.colidx, device="cuda:0")
+    B = len(srcs)
+    qs = fora.make_queries(srcs, alpha=alpha, eps=eps, k=k, seed=seed, n=g.n)
+    ws = fora.workspace(G, B)
+    ids = torch.empty((B, k), dtype=torch.int32, device="cuda:0")
+    vals = torch.empty((B, k), dtype=torch.float32, device="cuda:0")
+    log(f"workspace {ws.numel()/2**30:.2f} GiB for batch {B}")
+
+    for i in range(args.warmup):
+        fora.fora_ssppr_batch(G, qs, kmax=k, ws=ws, out=(ids, vals))
+        log(f"warmup {i+1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    step_times, walk_ms, stats0 = [], [], None
+    total_steps = total_walks = 0
+    t_all = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        res = fora.fora_ssppr_batch(G, qs, kmax=k, ws=ws, out=(ids, vals), stats=True)
+        torch.cuda.synchronize()
+        step_times.append(time.perf_counter() - ts)
+        st = res.stats
+        stats0 = st
+        total_steps += sum(s["steps"] for s in st)
+        total_walks += sum(s["walks"] for s in st)
+        walk_ms.append(st[0]["ms_walk"])
+        log(f"step {i+1}/{args.steps}: {step_times[-1]*1e3:.1f} ms "
+            f"(push {st[0]['ms_push']:.1f} plan {st[0]['ms_plan']:.1f} "
+            f"walk {st[0]['ms_walk']:.1f} topk {st[0]['ms_topk']:.1f})")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_all
+    steps_per_s = total_steps / elapsed
+    qps = B * args.steps / elapsed
+
+    per_launch_steps = total_steps / args.steps
+    per_launch_walks = total_walks / args.steps
+    walk_s = float(np.mean(walk_ms)) / 1e3
+    alg_bytes = BYTES_PER_STEP * per_launch_steps + BYTES_PER_WALK * per_launch_walks
+    achieved = alg_bytes / walk_s / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS,
+                    unit="GB/s", frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None,
+                    kernel="k_walks", bytes_per_launch=alg_bytes,
+                    avg_launch_ms=round(walk_s * 1e3, 3))
+
+    single = None
+    if not args.no_single:
+        ws1 = fora.workspace(G, 1)
+        o1 = (torch.empty(k, dtype=torch.int32, device="cuda:0"),
+              torch.empty(k, dtype=torch.float32, device="cuda:0"))
+        fora.fora_ssppr(G, int(srcs[0]), alpha, eps, k=k, seed=seed, ws=ws1, out=o1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s_steps = 0
+        for s in srcs:
+            r = fora.fora_ssppr(G, int(s), alpha, eps, k=k, seed=seed, ws=ws1, out=o1, stats=True)
+            s_steps += r.stats["steps"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        single = dict(queries_per_s=round(B / dt, 2), walk_steps_per_s=s_steps / dt,
+                      ms_per_query=round(dt / B * 1e3, 3))
+        log(f"plain single-query loop: {B/dt:.1f} q/s")
+        del ws1
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one source)...")
+        cpu = cpu_baseline(g, srcs[0], alpha, eps, k, seed)
+        log(f"cpu baseline: {cpu['seconds']:.1f}s")
+
+    out = {
+        "metric": METRIC, "value": steps_per_s, "unit": "walk-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{g.name}, {B} sources, batched", "n": g.n, "m": g.m,
+                   "sources": B, "alpha": alpha, "eps": eps, "delta": "1/n", "pf": "1/n",
+                   "k": k, "batch": B},
+        "queries_per_s": round(qps, 2),
+        "plain_single_query": single,
+        "phases_ms": {p: round(float(np.mean([stats0[0][p]])), 3)
+                      for p in ("ms_push", "ms_plan", "ms_walk", "ms_topk")},
+        "per_step": {"walks": per_launch_walks, "walk_steps": per_launch_steps,
+                     "edge_ops": sum(s["edge_ops"] for s in stats0),
+                     "rounds_max": max(s["rounds"] for s in stats0)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

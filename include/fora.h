@@ -1,0 +1,181 @@
+/*
+ * fora.h -- C ABI of the MI355X (gfx950) implementation of FORA approximate
+ * single-source Personalized PageRank (Wang et al., TODS 2019):
+ * synchronous forward push to r_max, then Philox-keyed random walks from
+ * every node with residue, then top-k over reserve + walk estimate.
+ *
+ * Conventions
+ *  - Every call returns an int status (FORA_OK or a negative FORA_E_* code);
+ *    fora_last_error() gives a message for the calling thread's last failure.
+ *  - "d_" pointers are device (HBM) pointers, "h_" pointers host pointers.
+ *  - Device memory for inputs, outputs and the per-call workspace is owned by
+ *    the caller; the hot-path calls never allocate. Only fora_build_csr
+ *    allocates (a derived per-node table of 8 bytes per node), released by
+ *    fora_free_graph.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    The push phase checks the frontier size from the host between groups of
+ *    rounds, and every query call reads its device error flags at the end, so
+ *    query calls return after their work has completed.
+ *  - A workspace may be used by one call at a time; calls that share a
+ *    workspace must be ordered (same stream or explicit synchronisation).
+ *
+ * Notation (paper, notation table): n nodes, m edges, d(v) out-degree,
+ * alpha stop probability, eps relative error, delta threshold, p_f failure
+ * probability, r residue, q ("pi-circle") reserve, r_max residue threshold.
+ */
+#ifndef FORA_H_
+#define FORA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FORA_OK = 0,
+  FORA_E_ARG = -1,      /* an argument is out of its documented range      */
+  FORA_E_GRAPH = -2,    /* the CSR graph is malformed or has a dangling node */
+  FORA_E_NOMEM = -3,    /* workspace too small, or an allocation failed    */
+  FORA_E_HIP = -4,      /* a HIP runtime call failed                       */
+  FORA_E_OVERFLOW = -5  /* a count exceeds the widths documented below     */
+};
+
+/* Opaque handle to a validated graph. It BORROWS the caller's CSR arrays:
+ * keep them alive and unchanged until fora_free_graph. */
+typedef struct fora_graph fora_graph;
+
+/* Per-query counters. Filled when a stats pointer is given. */
+typedef struct fora_stats {
+  int32_t rounds;          /* synchronous push rounds with a non-empty frontier */
+  int32_t term_violations; /* residues above r_max*d(v) after the push (0)     */
+  int64_t pushes;          /* frontier entries pushed, over all rounds         */
+  int64_t edge_ops;        /* residue increments applied (sum of d over pushes)*/
+  int64_t plan_entries;    /* nodes with r(v) > 0 (walk plan length)           */
+  uint64_t walks;          /* W = sum over v of omega_v                        */
+  uint64_t steps;          /* walk moves (edge traversals) over all walks      */
+  double r_sum;            /* sum of residues after the push (FP64 sum)        */
+  double rmax;             /* r_max used                                       */
+  double omega_unit;       /* (2 eps/3 + 2) ln(2/p_f) / (eps^2 delta)          */
+  uint32_t t_alpha;        /* floor(alpha * 2^32)                              */
+  float ms_push;           /* phase times from HIP events on the call's stream */
+  float ms_plan;           /* (for a batch: the whole batch's phase, repeated  */
+  float ms_walk;           /*  in every entry); ms_walk spans exactly the walk */
+  float ms_topk;           /*  kernel launch                                   */
+  uint32_t reserved;
+} fora_stats;
+
+/* One query of a batch. */
+typedef struct fora_query {
+  int32_t src;   /* source node, 0 <= src < n                                */
+  int32_t k;     /* 1 <= k <= min(n, FORA_MAX_K)                             */
+  double alpha;  /* 0 < alpha < 1                                            */
+  double eps;    /* 0 < eps < 1                                              */
+  double delta;  /* 0 < delta <= 1                                           */
+  double pf;     /* 0 < pf < 1                                               */
+  double rmax;   /* > 0: use this r_max; <= 0: eqn:rmax (section 3.2)        */
+  uint64_t seed; /* low 32 bits form the second Philox key word              */
+} fora_query;
+
+#define FORA_MAX_K 4096
+#define FORA_MAX_BATCH 4096
+
+/* Dense per-query arrays inside a workspace, for inspection. Query b's row
+ * starts at b*n. Valid after a call on that workspace has completed. */
+typedef struct fora_views {
+  float *residue;             /* r(s, v), FP32 [batch][n]                     */
+  float *reserve;             /* q(s, v), FP32 [batch][n]                     */
+  uint32_t *walk_count;       /* walks ending at v, [batch][n]                */
+  uint64_t *walk_weight_fx;   /* sum of walk weights ending at v, unsigned
+                                 fixed point with 62 fraction bits [batch][n] */
+  float *pi_hat;              /* q + walk weight, FP32 [batch][n]             */
+} fora_views;
+
+const char *fora_last_error(void);
+
+/* Graph ingest (section 2.1: a directed graph stored as out-adjacency lists).
+ * d_rowptr: int32[n+1], d_colidx: int32[m], device. Checks on the device that
+ * rowptr[0] = 0, rowptr[n] = m, rowptr is non-decreasing, every target is in
+ * [0, n), and every node has out-degree >= 1 (a walk must be able to move and
+ * Algorithm 1 divides by |N_out(v)|). Requires 1 <= n and m < 2^31.
+ * Errors: FORA_E_ARG (sizes), FORA_E_GRAPH (content), FORA_E_HIP, FORA_E_NOMEM.
+ * Waits for the check to finish. */
+int fora_build_csr(int32_t n, int64_t m, const int32_t *d_rowptr,
+                   const int32_t *d_colidx, void *stream, fora_graph **out);
+int fora_free_graph(fora_graph *g);
+int fora_graph_info(const fora_graph *g, int32_t *n, int64_t *m,
+                    int32_t *max_degree);
+
+/* Bytes of workspace for `batch` concurrent queries (1..FORA_MAX_BATCH). */
+int fora_workspace_size(const fora_graph *g, int32_t batch, size_t *bytes);
+int fora_workspace_views(const fora_graph *g, int32_t batch, void *d_ws,
+                         fora_views *views);
+
+/* Whole-graph FORA (Algorithm 2) for one source, then top-k (section 5,
+ * selection over the whole-graph estimate).
+ *  push: synchronous Forward Push (Algorithm 1, every node over its
+ *    threshold in one round) down to r_max (eqn:rmax unless opt_rmax > 0);
+ *  walks: omega_v = ceil(r(v) * omega_unit) walks from each v with
+ *    r(v) > 0, each ending at t adding r(v)/omega_v to pi_hat(t);
+ *  top-k: ids sorted by (pi_hat descending, id ascending).
+ * Output d_topk_ids int32[k], d_topk_vals float[k] (FP32 pi_hat). If fewer
+ * than k nodes have pi_hat > 0 the rest are the lowest unused ids, value 0.
+ * h_stats (nullable) makes the call wait and fill the counters.
+ * Errors: FORA_E_ARG for any parameter outside the ranges of fora_query,
+ * FORA_E_NOMEM if ws_bytes < fora_workspace_size(g, 1),
+ * FORA_E_OVERFLOW if W >= 2^32 (walk counts are 32-bit) or some
+ * omega_v >= 2^32, FORA_E_HIP. */
+int fora_ssppr(const fora_graph *g, int32_t src, double alpha, double eps,
+               double delta, double pf, int32_t k, double opt_rmax,
+               uint64_t seed, void *d_ws, size_t ws_bytes,
+               int32_t *d_topk_ids, float *d_topk_vals, fora_stats *h_stats,
+               void *stream);
+
+/* The same for `batch` queries in one launch sequence: all queries' push
+ * rounds, walk plans, walks and selections run in shared kernels. Query b's
+ * result is written to d_ids[b*kmax ...], d_vals[b*kmax ...]; kmax must be at
+ * least every query's k. Each query's result equals what fora_ssppr returns
+ * for it (walk counts bit-identical given identical residues). h_stats
+ * (nullable) is an array of `batch` entries. */
+int fora_ssppr_batch(const fora_graph *g, int32_t batch,
+                     const fora_query *h_queries, int32_t kmax, void *d_ws,
+                     size_t ws_bytes, int32_t *d_ids, float *d_vals,
+                     fora_stats *h_stats, void *stream);
+
+/* ---- step-level entry points (used to compare each phase on its own) ---- */
+
+/* Only the push phase of fora_ssppr for one source (Algorithm 1,
+ * synchronous rounds). Results in the workspace views (row 0).
+ * h_round_sizes (nullable, max_rounds entries) receives |F_t|; d_frontiers
+ * (nullable, device int32, frontier_cap entries) receives the frontiers of
+ * all rounds back to back, each round's set in ascending id order.
+ * Waits for completion. FORA_E_OVERFLOW if max_rounds or frontier_cap is too
+ * small. */
+int fora_push_only(const fora_graph *g, int32_t src, double alpha, double rmax,
+                   void *d_ws, size_t ws_bytes, int32_t max_rounds,
+                   int32_t *h_round_sizes, int32_t *d_frontiers,
+                   int64_t frontier_cap, fora_stats *h_stats, void *stream);
+
+/* Only the walk phase for a caller-given plan (Algorithm 2's walk loop):
+ * entries (d_v[e], d_omega[e], d_w[e]) with d_v strictly increasing,
+ * 1 <= d_omega[e] < 2^32, d_w[e] > 0 (FP64). Walks use Philox key
+ * (key0, key1) and stop threshold floor(alpha * 2^32). Endpoint counts go to
+ * the workspace view walk_count (row 0), weights to walk_weight_fx as
+ * round(d_w[e] * 2^62) per walk. h_steps (nullable) receives the move count
+ * and makes the call wait. At most n entries. */
+int fora_walk_only(const fora_graph *g, int64_t entries, const int32_t *d_v,
+                   const uint64_t *d_omega, const double *d_w, uint32_t key0,
+                   uint32_t key1, double alpha, void *d_ws, size_t ws_bytes,
+                   uint64_t *h_steps, void *stream);
+
+/* Philox4x32-10 (Salmon et al., SC'11) blocks on the device: d_out[4i..4i+3]
+ * = Philox(d_ctr[4i..4i+3], (key0, key1)). */
+int fora_philox(int64_t count, const uint32_t *d_ctr, uint32_t key0,
+                uint32_t key1, uint32_t *d_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FORA_H_ */

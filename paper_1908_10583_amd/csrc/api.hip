@@ -1,0 +1,542 @@
+// C ABI of the FORA library: argument checks, host-side FP64 planning of the
+// per-query constants, workspace layout, and the launch sequence
+//   zero state -> init -> push rounds -> plan -> walks -> estimate + top-k.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+struct fora_graph {
+  fora::GraphDev dev;
+  int2* info_owned = nullptr;
+  int* flags_owned = nullptr;  // 2 ints: check flags, max degree
+  int device = 0;
+  int cus = 256;
+  // pinned host slots for the small read-backs of the push loop
+  std::mutex mu;
+  uint64_t* pinned = nullptr;
+  std::vector<int> free_slots;
+};
+
+namespace fora {
+namespace {
+
+constexpr int kPinnedSlots = 64;
+constexpr int kMaxRounds = 20000;
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define FORA_HIP(expr)                                                                \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(FORA_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct PinnedSlot {
+  fora_graph* g;
+  int slot;
+  uint64_t* p;
+  explicit PinnedSlot(fora_graph* gr) : g(gr), slot(-1), p(nullptr) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (!g->free_slots.empty()) {
+      slot = g->free_slots.back();
+      g->free_slots.pop_back();
+      p = g->pinned + (size_t)slot * 8;
+    }
+  }
+  ~PinnedSlot() {
+    if (slot >= 0) {
+      std::lock_guard<std::mutex> lk(g->mu);
+      g->free_slots.push_back(slot);
+    }
+  }
+};
+
+int check_query(const fora_graph* g, const fora_query& q) {
+  const int32_t n = g->dev.n;
+  if (q.src < 0 || q.src >= n) return fail(FORA_E_ARG, "source out of range");
+  if (!(q.alpha > 0.0 && q.alpha < 1.0)) return fail(FORA_E_ARG, "alpha must be in (0,1)");
+  if (!(q.eps > 0.0 && q.eps < 1.0)) return fail(FORA_E_ARG, "eps must be in (0,1)");
+  if (!(q.delta > 0.0 && q.delta <= 1.0)) return fail(FORA_E_ARG, "delta must be in (0,1]");
+  if (!(q.pf > 0.0 && q.pf < 1.0)) return fail(FORA_E_ARG, "pf must be in (0,1)");
+  if (q.k < 1 || q.k > n || q.k > FORA_MAX_K) return fail(FORA_E_ARG, "k must be in [1, min(n, FORA_MAX_K)]");
+  if (!(q.rmax <= 0.0 || std::isfinite(q.rmax))) return fail(FORA_E_ARG, "rmax must be finite");
+  return FORA_OK;
+}
+
+// Algorithm 2 and eqn:rmax (section 3.2), in FP64 on the host:
+//   omega_unit = (2 eps/3 + 2) ln(2/p_f) / (eps^2 delta)
+//   r_max      = eps / sqrt(m) * sqrt(delta / ((2 eps/3 + 2) ln(2/p_f))),
+//                or eps^2 delta / ((2 eps/3 + 2) ln(2/p_f)) when m r_max > 1.
+QueryDev plan_query(const fora_graph* g, const fora_query& q) {
+  QueryDev d{};
+  const double c = 2.0 * q.eps / 3.0 + 2.0;
+  const double L = std::log(2.0 / q.pf);
+  const double cl = c * L;
+  d.omega_unit = cl / ((q.eps * q.eps) * q.delta);
+  double rmax = q.eps / std::sqrt((double)g->dev.m) * std::sqrt(q.delta / cl);
+  if ((double)g->dev.m * rmax > 1.0) rmax = (q.eps * q.eps) * q.delta / cl;
+  if (q.rmax > 0.0) rmax = q.rmax;
+  d.rmax = rmax;
+  d.alpha = q.alpha;
+  d.src = q.src;
+  d.k = q.k;
+  d.key0 = (uint32_t)q.src;
+  d.key1 = (uint32_t)(q.seed & 0xFFFFFFFFull);
+  d.t_alpha = (uint32_t)std::floor(std::ldexp(q.alpha, 32));
+  return d;
+}
+
+int error_code_from_flags(int flags) {
+  if (flags & kErrOmegaOverflow)
+    return fail(FORA_E_OVERFLOW, "walk count overflow (omega_v >= 2^32 or W >= 2^32)");
+  if (flags & kErrFrontierOverflow) return fail(FORA_E_OVERFLOW, "frontier overflow");
+  if (flags & kErrLogOverflow) return fail(FORA_E_OVERFLOW, "frontier log capacity too small");
+  if (flags & kErrTopk) return fail(FORA_E_HIP, "top-k selection inconsistent");
+  return FORA_OK;
+}
+
+int walk_blocks(const fora_graph* g) { return g->cus * 8; }
+int push_blocks(const fora_graph* g) { return g->cus * 4; }
+
+struct Call {
+  Layout L;
+  Ws w;
+};
+
+int prepare(const fora_graph* g, int batch, void* d_ws, size_t ws_bytes, Call& c) {
+  if (!g) return fail(FORA_E_ARG, "null graph");
+  if (batch < 1 || batch > FORA_MAX_BATCH) return fail(FORA_E_ARG, "batch out of range");
+  if (!d_ws) return fail(FORA_E_ARG, "null workspace");
+  if (((uintptr_t)d_ws & 255) != 0) return fail(FORA_E_ARG, "workspace must be 256-byte aligned");
+  c.L = make_layout(g->dev.n, batch);
+  if (ws_bytes < c.L.total) return fail(FORA_E_NOMEM, "workspace too small");
+  c.w = carve(c.L, d_ws);
+  return FORA_OK;
+}
+
+// Push rounds until the frontier is empty; the host checks the frontier size
+// after every group of rounds.
+int run_push(fora_graph* g, const Call& c, int batch, hipStream_t s, bool stats,
+             int32_t* log, int64_t log_cap, int* rounds_out) {
+  PinnedSlot ps(g);
+  if (!ps.p) return fail(FORA_E_NOMEM, "too many concurrent calls on one graph");
+  int t = 0, group = 4;
+  for (;;) {
+    for (int i = 0; i < group; ++i, ++t)
+      FORA_HIP(launch_push_round(g->dev, c.w, batch, t, push_blocks(g), stats, log, log_cap, s));
+    FORA_HIP(hipMemcpyAsync(ps.p, &c.w.ctrl->fr_cnt[t & 1], sizeof(uint64_t),
+                            hipMemcpyDeviceToHost, s));
+    FORA_HIP(hipStreamSynchronize(s));
+    if (*ps.p == 0) break;
+    if (t >= kMaxRounds) return fail(FORA_E_OVERFLOW, "push did not converge");
+    group = std::min(group * 2, 16);
+  }
+  if (rounds_out) *rounds_out = t;
+  return FORA_OK;
+}
+
+// Events bracketing the phases of one call (created only when stats are asked).
+struct PhaseEvents {
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool on = false;
+  explicit PhaseEvents(bool enable) : on(enable) {
+    if (!on) return;
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) {
+        on = false;
+        break;
+      }
+  }
+  ~PhaseEvents() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  void mark(int i, hipStream_t s) {
+    if (on) (void)hipEventRecord(ev[i], s);
+  }
+  float ms(int i) const {
+    float t = 0.f;
+    if (on) (void)hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+    return t;
+  }
+};
+
+int finish(fora_graph* g, const Call& c, int batch, hipStream_t s, fora_stats* h_stats,
+           const std::vector<QueryDev>& qd, const PhaseEvents* pe = nullptr) {
+  int flags = 0;
+  FORA_HIP(hipMemcpyAsync(&flags, &c.w.ctrl->error, sizeof(int), hipMemcpyDeviceToHost, s));
+  std::vector<QueryStatsDev> qs;
+  if (h_stats) {
+    qs.resize(batch);
+    FORA_HIP(hipMemcpyAsync(qs.data(), c.w.qstats, sizeof(QueryStatsDev) * batch,
+                            hipMemcpyDeviceToHost, s));
+  }
+  FORA_HIP(hipStreamSynchronize(s));
+  const int rc = error_code_from_flags(flags);
+  if (rc != FORA_OK) return rc;
+  if (h_stats) {
+    for (int b = 0; b < batch; ++b) {
+      fora_stats& o = h_stats[b];
+      std::memset(&o, 0, sizeof(o));
+      o.rounds = qs[b].rounds;
+      o.term_violations = qs[b].term_violations;
+      o.pushes = (int64_t)qs[b].pushes;
+      o.edge_ops = (int64_t)qs[b].edge_ops;
+      o.plan_entries = (int64_t)qs[b].entries;
+      o.walks = qs[b].walks;
+      o.steps = qs[b].steps;
+      o.r_sum = qs[b].r_sum;
+      o.rmax = qd[b].rmax;
+      o.omega_unit = qd[b].omega_unit;
+      o.t_alpha = qd[b].t_alpha;
+      if (pe && pe->on) {
+        o.ms_push = pe->ms(0);
+        o.ms_plan = pe->ms(1);
+        o.ms_walk = pe->ms(2);
+        o.ms_topk = pe->ms(3);
+      }
+    }
+  }
+  (void)g;
+  return FORA_OK;
+}
+
+int run_queries(fora_graph* g, int batch, const fora_query* qs, int kmax, void* d_ws,
+                size_t ws_bytes, int32_t* d_ids, float* d_vals, fora_stats* h_stats,
+                hipStream_t s) {
+  if (!qs) return fail(FORA_E_ARG, "null queries");
+  if (!d_ids || !d_vals) return fail(FORA_E_ARG, "null output");
+  Call c;
+  int rc = prepare(g, batch, d_ws, ws_bytes, c);
+  if (rc != FORA_OK) return rc;
+  std::vector<QueryDev> qd(batch);
+  for (int b = 0; b < batch; ++b) {
+    rc = check_query(g, qs[b]);
+    if (rc != FORA_OK) return rc;
+    if (qs[b].k > kmax) return fail(FORA_E_ARG, "kmax smaller than a query's k");
+    qd[b] = plan_query(g, qs[b]);
+  }
+  FORA_HIP(hipSetDevice(g->device));
+  FORA_HIP(launch_fill_zero((char*)d_ws + c.L.zero_begin, c.L.zero_end - c.L.zero_begin, s));
+  FORA_HIP(hipMemcpyAsync(c.w.queries, qd.data(), sizeof(QueryDev) * batch,
+                          hipMemcpyHostToDevice, s));
+  PhaseEvents pe(h_stats != nullptr);
+  pe.mark(0, s);
+  FORA_HIP(launch_init_queries(g->dev, c.w, batch, s));
+  rc = run_push(g, c, batch, s, true, nullptr, 0, nullptr);
+  if (rc != FORA_OK) return rc;
+  pe.mark(1, s);
+  FORA_HIP(launch_plan(g->dev, c.w, c.L, batch, s));
+  pe.mark(2, s);
+  FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), s));
+  pe.mark(3, s);
+  FORA_HIP(launch_topk(g->dev, c.w, c.L, batch, kmax, d_ids, d_vals, s));
+  pe.mark(4, s);
+  return finish(g, c, batch, s, h_stats, qd, &pe);
+}
+
+}  // namespace
+
+Layout make_layout(int32_t n, int32_t batch) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = align_up(off, 256);
+    const size_t o = off;
+    off += bytes;
+    return o;
+  };
+  const size_t cap = (size_t)batch * (size_t)n;
+  L.cap = (int64_t)cap;
+  L.tiles_per_row = (n + kPlanTile - 1) / kPlanTile;
+  L.plan_tiles = L.tiles_per_row * batch;
+  L.topk_blocks = (n + kTopkTile - 1) / kTopkTile;
+  // region cleared at the start of every call
+  L.ctrl = take(sizeof(Ctrl));
+  L.zero_begin = L.ctrl;
+  L.qstats = take(sizeof(QueryStatsDev) * batch);
+  L.r = take(4 * cap);
+  L.q = take(4 * cap);
+  L.cnt = take(4 * cap);
+  L.acc = take(8 * cap);
+  L.hist = take(4 * (size_t)kHistBins * batch);
+  L.cand_cnt = take(4 * (size_t)batch);
+  L.zero_end = align_up(off, 256);
+  // written before being read
+  L.queries = take(sizeof(QueryDev) * batch);
+  L.pi = take(4 * cap);
+  L.fr0 = take(8 * cap);
+  L.fr1 = take(8 * cap);
+  L.frx = take(4 * cap);
+  L.plan_gi = take(8 * cap);
+  L.plan_off = take(8 * (cap + 1));
+  L.plan_wfx = take(8 * cap);
+  L.tile_cnt = take(4 * (size_t)L.plan_tiles);
+  L.tile_walks = take(8 * (size_t)L.plan_tiles);
+  L.tile_eoff = take(8 * (size_t)L.plan_tiles);
+  L.tile_woff = take(8 * (size_t)L.plan_tiles);
+  L.sel = take(16 * (size_t)batch);
+  L.cand_key = take(4 * (size_t)FORA_MAX_K * batch);
+  L.cand_id = take(4 * (size_t)FORA_MAX_K * batch);
+  L.blk_ties = take(4 * (size_t)L.topk_blocks * batch);
+  L.total = align_up(off, 256);
+  return L;
+}
+
+Ws carve(const Layout& L, void* base) {
+  char* p = (char*)base;
+  Ws w{};
+  w.ctrl = (Ctrl*)(p + L.ctrl);
+  w.qstats = (QueryStatsDev*)(p + L.qstats);
+  w.queries = (QueryDev*)(p + L.queries);
+  w.r = (float*)(p + L.r);
+  w.q = (float*)(p + L.q);
+  w.cnt = (uint32_t*)(p + L.cnt);
+  w.acc = (u64*)(p + L.acc);
+  w.pi = (float*)(p + L.pi);
+  w.fr[0] = (u64*)(p + L.fr0);
+  w.fr[1] = (u64*)(p + L.fr1);
+  w.frx = (float*)(p + L.frx);
+  w.plan_gi = (u64*)(p + L.plan_gi);
+  w.plan_off = (u64*)(p + L.plan_off);
+  w.plan_wfx = (u64*)(p + L.plan_wfx);
+  w.tile_cnt = (uint32_t*)(p + L.tile_cnt);
+  w.tile_walks = (u64*)(p + L.tile_walks);
+  w.tile_eoff = (u64*)(p + L.tile_eoff);
+  w.tile_woff = (u64*)(p + L.tile_woff);
+  w.hist = (uint32_t*)(p + L.hist);
+  w.sel = (uint32_t*)(p + L.sel);
+  w.cand_key = (uint32_t*)(p + L.cand_key);
+  w.cand_id = (int32_t*)(p + L.cand_id);
+  w.cand_cnt = (uint32_t*)(p + L.cand_cnt);
+  w.blk_ties = (uint32_t*)(p + L.blk_ties);
+  return w;
+}
+
+int device_cu_count() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 256;
+  return cus > 0 ? cus : 256;
+}
+
+}  // namespace fora
+
+using namespace fora;
+
+extern "C" {
+
+const char* fora_last_error(void) { return g_err.c_str(); }
+
+int fora_build_csr(int32_t n, int64_t m, const int32_t* d_rowptr, const int32_t* d_colidx,
+                   void* stream, fora_graph** out) {
+  if (!out) return fail(FORA_E_ARG, "null output handle");
+  *out = nullptr;
+  if (n < 1) return fail(FORA_E_ARG, "n must be >= 1");
+  if (m < 0 || m >= (int64_t)1 << 31) return fail(FORA_E_ARG, "m must be in [0, 2^31)");
+  if (!d_rowptr || (m > 0 && !d_colidx)) return fail(FORA_E_ARG, "null CSR array");
+  hipStream_t s = (hipStream_t)stream;
+  fora_graph* g = new fora_graph();
+  g->dev.n = n;
+  g->dev.m = m;
+  g->dev.rowptr = d_rowptr;
+  g->dev.colidx = d_colidx;
+  auto cleanup = [&](int code, const std::string& msg) {
+    if (g->info_owned) (void)hipFree(g->info_owned);
+    if (g->flags_owned) (void)hipFree(g->flags_owned);
+    if (g->pinned) (void)hipHostFree(g->pinned);
+    delete g;
+    return fail(code, msg);
+  };
+  if (hipGetDevice(&g->device) != hipSuccess) return cleanup(FORA_E_HIP, "hipGetDevice failed");
+  g->cus = device_cu_count();
+  if (hipMalloc(&g->info_owned, sizeof(int2) * (size_t)n) != hipSuccess)
+    return cleanup(FORA_E_NOMEM, "hipMalloc of the node table failed");
+  if (hipMalloc(&g->flags_owned, 2 * sizeof(int)) != hipSuccess)
+    return cleanup(FORA_E_NOMEM, "hipMalloc failed");
+  if (hipHostMalloc((void**)&g->pinned, sizeof(uint64_t) * 8 * kPinnedSlots, 0) != hipSuccess)
+    return cleanup(FORA_E_NOMEM, "hipHostMalloc failed");
+  for (int i = kPinnedSlots - 1; i >= 0; --i) g->free_slots.push_back(i);
+  g->dev.info = g->info_owned;
+  int host_flags[2] = {0, 0};
+  if (hipMemcpyAsync(g->flags_owned, host_flags, sizeof(host_flags), hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      launch_graph_check(g->dev, g->flags_owned, g->flags_owned + 1, g->info_owned, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(host_flags, g->flags_owned, sizeof(host_flags), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return cleanup(FORA_E_HIP, std::string("graph check failed: ") +
+                                   hipGetErrorString(hipGetLastError()));
+  if (host_flags[0] & kErrGraphRowptr) return cleanup(FORA_E_GRAPH, "malformed rowptr");
+  if (host_flags[0] & kErrGraphTarget) return cleanup(FORA_E_GRAPH, "target id out of range");
+  if (host_flags[0] & kErrGraphDangling)
+    return cleanup(FORA_E_GRAPH, "a node has out-degree 0 (dangling)");
+  g->dev.max_deg = host_flags[1];
+  *out = g;
+  return FORA_OK;
+}
+
+int fora_free_graph(fora_graph* g) {
+  if (!g) return FORA_OK;
+  if (g->info_owned) (void)hipFree(g->info_owned);
+  if (g->flags_owned) (void)hipFree(g->flags_owned);
+  if (g->pinned) (void)hipHostFree(g->pinned);
+  delete g;
+  return FORA_OK;
+}
+
+int fora_graph_info(const fora_graph* g, int32_t* n, int64_t* m, int32_t* max_degree) {
+  if (!g) return fail(FORA_E_ARG, "null graph");
+  if (n) *n = g->dev.n;
+  if (m) *m = g->dev.m;
+  if (max_degree) *max_degree = g->dev.max_deg;
+  return FORA_OK;
+}
+
+int fora_workspace_size(const fora_graph* g, int32_t batch, size_t* bytes) {
+  if (!g || !bytes) return fail(FORA_E_ARG, "null argument");
+  if (batch < 1 || batch > FORA_MAX_BATCH) return fail(FORA_E_ARG, "batch out of range");
+  *bytes = make_layout(g->dev.n, batch).total;
+  return FORA_OK;
+}
+
+int fora_workspace_views(const fora_graph* g, int32_t batch, void* d_ws, fora_views* v) {
+  if (!g || !d_ws || !v) return fail(FORA_E_ARG, "null argument");
+  if (batch < 1 || batch > FORA_MAX_BATCH) return fail(FORA_E_ARG, "batch out of range");
+  const Layout L = make_layout(g->dev.n, batch);
+  const Ws w = carve(L, d_ws);
+  v->residue = w.r;
+  v->reserve = w.q;
+  v->walk_count = w.cnt;
+  v->walk_weight_fx = (uint64_t*)w.acc;
+  v->pi_hat = w.pi;
+  return FORA_OK;
+}
+
+int fora_ssppr(const fora_graph* g, int32_t src, double alpha, double eps, double delta,
+               double pf, int32_t k, double opt_rmax, uint64_t seed, void* d_ws,
+               size_t ws_bytes, int32_t* d_topk_ids, float* d_topk_vals, fora_stats* h_stats,
+               void* stream) {
+  if (!g) return fail(FORA_E_ARG, "null graph");
+  fora_query q{};
+  q.src = src;
+  q.k = k;
+  q.alpha = alpha;
+  q.eps = eps;
+  q.delta = delta;
+  q.pf = pf;
+  q.rmax = opt_rmax;
+  q.seed = seed;
+  return run_queries(const_cast<fora_graph*>(g), 1, &q, k, d_ws, ws_bytes, d_topk_ids,
+                     d_topk_vals, h_stats, (hipStream_t)stream);
+}
+
+int fora_ssppr_batch(const fora_graph* g, int32_t batch, const fora_query* h_queries,
+                     int32_t kmax, void* d_ws, size_t ws_bytes, int32_t* d_ids, float* d_vals,
+                     fora_stats* h_stats, void* stream) {
+  if (kmax < 1 || kmax > FORA_MAX_K) return fail(FORA_E_ARG, "kmax out of range");
+  return run_queries(const_cast<fora_graph*>(g), batch, h_queries, kmax, d_ws, ws_bytes, d_ids,
+                     d_vals, h_stats, (hipStream_t)stream);
+}
+
+int fora_push_only(const fora_graph* gc, int32_t src, double alpha, double rmax, void* d_ws,
+                   size_t ws_bytes, int32_t max_rounds, int32_t* h_round_sizes,
+                   int32_t* d_frontiers, int64_t frontier_cap, fora_stats* h_stats,
+                   void* stream) {
+  fora_graph* g = const_cast<fora_graph*>(gc);
+  hipStream_t s = (hipStream_t)stream;
+  Call c;
+  int rc = prepare(g, 1, d_ws, ws_bytes, c);
+  if (rc != FORA_OK) return rc;
+  if (src < 0 || src >= g->dev.n) return fail(FORA_E_ARG, "source out of range");
+  if (!(alpha > 0.0 && alpha < 1.0)) return fail(FORA_E_ARG, "alpha must be in (0,1)");
+  if (!(rmax > 0.0 && std::isfinite(rmax))) return fail(FORA_E_ARG, "rmax must be > 0");
+  if (max_rounds < 0) return fail(FORA_E_ARG, "max_rounds < 0");
+  if (d_frontiers && frontier_cap < 0) return fail(FORA_E_ARG, "frontier_cap < 0");
+  QueryDev qd{};
+  qd.src = src;
+  qd.k = 1;
+  qd.alpha = alpha;
+  qd.rmax = rmax;
+  qd.omega_unit = 1.0;
+  FORA_HIP(hipSetDevice(g->device));
+  FORA_HIP(launch_fill_zero((char*)d_ws + c.L.zero_begin, c.L.zero_end - c.L.zero_begin, s));
+  FORA_HIP(hipMemcpyAsync(c.w.queries, &qd, sizeof(qd), hipMemcpyHostToDevice, s));
+  FORA_HIP(launch_init_queries(g->dev, c.w, 1, s));
+  int rounds = 0;
+  rc = run_push(g, c, 1, s, true, d_frontiers, d_frontiers ? frontier_cap : 0, &rounds);
+  if (rc != FORA_OK) return rc;
+  std::vector<QueryDev> qv(1, qd);
+  fora_stats st{};
+  rc = finish(g, c, 1, s, &st, qv);
+  if (rc != FORA_OK) return rc;
+  if (st.rounds > max_rounds && h_round_sizes)
+    return fail(FORA_E_OVERFLOW, "more rounds than max_rounds");
+  if (st.rounds > kMaxRoundsLogged && h_round_sizes)
+    return fail(FORA_E_OVERFLOW, "too many rounds to log");
+  if (h_round_sizes && st.rounds > 0) {
+    std::vector<uint64_t> rs(st.rounds);
+    FORA_HIP(hipMemcpy(rs.data(), c.w.ctrl->round_size, sizeof(uint64_t) * st.rounds,
+                       hipMemcpyDeviceToHost));
+    for (int i = 0; i < st.rounds; ++i) h_round_sizes[i] = (int32_t)rs[i];
+  }
+  if (h_stats) *h_stats = st;
+  return FORA_OK;
+}
+
+int fora_walk_only(const fora_graph* gc, int64_t entries, const int32_t* d_v,
+                   const uint64_t* d_omega, const double* d_w, uint32_t key0, uint32_t key1,
+                   double alpha, void* d_ws, size_t ws_bytes, uint64_t* h_steps,
+                   void* stream) {
+  fora_graph* g = const_cast<fora_graph*>(gc);
+  hipStream_t s = (hipStream_t)stream;
+  Call c;
+  int rc = prepare(g, 1, d_ws, ws_bytes, c);
+  if (rc != FORA_OK) return rc;
+  if (entries < 0 || entries > g->dev.n) return fail(FORA_E_ARG, "entries must be in [0, n]");
+  if (entries > 0 && (!d_v || !d_omega || !d_w)) return fail(FORA_E_ARG, "null plan array");
+  if (!(alpha > 0.0 && alpha < 1.0)) return fail(FORA_E_ARG, "alpha must be in (0,1)");
+  QueryDev qd{};
+  qd.key0 = key0;
+  qd.key1 = key1;
+  qd.alpha = alpha;
+  qd.t_alpha = (uint32_t)std::floor(std::ldexp(alpha, 32));
+  FORA_HIP(hipSetDevice(g->device));
+  FORA_HIP(launch_fill_zero((char*)d_ws + c.L.zero_begin, c.L.zero_end - c.L.zero_begin, s));
+  FORA_HIP(hipMemcpyAsync(c.w.queries, &qd, sizeof(qd), hipMemcpyHostToDevice, s));
+  if (entries > 0) {
+    FORA_HIP(launch_walk_plan_from_host(g->dev, c.w, entries, d_v, d_omega, d_w, s));
+    FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), s));
+  }
+  std::vector<QueryDev> qv(1, qd);
+  fora_stats st{};
+  rc = finish(g, c, 1, s, &st, qv);
+  if (rc != FORA_OK) return rc;
+  if (h_steps) *h_steps = st.steps;
+  return FORA_OK;
+}
+
+int fora_philox(int64_t count, const uint32_t* d_ctr, uint32_t key0, uint32_t key1,
+                uint32_t* d_out, void* stream) {
+  if (count < 0) return fail(FORA_E_ARG, "count < 0");
+  if (count > 0 && (!d_ctr || !d_out)) return fail(FORA_E_ARG, "null array");
+  FORA_HIP(launch_philox(count, d_ctr, key0, key1, d_out, (hipStream_t)stream));
+  return FORA_OK;
+}
+
+}  // extern "C"

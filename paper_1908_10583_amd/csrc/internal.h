@@ -1,0 +1,178 @@
+// Internal declarations of the FORA HIP library (gfx950).
+//
+// Data layout in HBM (per call, carved from the caller's workspace):
+//   ctrl      one Ctrl block: frontier counters, walk work queue, error flags
+//   qstats    QueryStats[batch]: per-query counters (device side)
+//   queries   QueryDev[batch]: per-query constants computed on the host
+//   r, q      float[batch][n]   residue / reserve (FP32)
+//   cnt       uint32[batch][n]  walk end-point counts
+//   acc       uint64[batch][n]  walk weights, fixed point (62 fraction bits)
+//   pi        float[batch][n]   q + acc, the estimate
+//   fr0/fr1   uint64[batch*n]   frontier entries (query << 32 | node)
+//   frx       float[batch*n]    per-frontier-entry increment (1-alpha) x / d
+//   plan_*    walk plan: entry (query << 32 | node), walk offset, weight
+//   tiles     per-tile counts and offsets for the plan scan
+//   topk      histograms, selection state and candidates
+// Graph: rowptr/colidx borrowed from the caller, plus an owned int2 table
+// info[v] = {rowptr[v], d(v)} so that a walk step reads one 8-byte record.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "fora.h"
+
+namespace fora {
+
+typedef unsigned long long u64;
+
+constexpr int kMaxRoundsLogged = 4096;
+constexpr int kPlanTile = 2048;        // nodes per plan tile (256 threads x 8)
+constexpr int kTopkTile = 4096;        // nodes per top-k block
+constexpr int kHistBins = 2048;        // 11-bit radix digits
+constexpr int kWalkChunk = 512;        // walk ids per work-queue grab
+constexpr double kFx = 4611686018427387904.0;  // 2^62
+
+// Error flags raised by kernels.
+enum : int {
+  kErrFrontierOverflow = 1,
+  kErrOmegaOverflow = 2,
+  kErrLogOverflow = 4,
+  kErrGraphRowptr = 8,
+  kErrGraphTarget = 16,
+  kErrGraphDangling = 32,
+  kErrTopk = 64,
+};
+
+struct QueryDev {
+  int32_t src;
+  int32_t k;
+  uint32_t key0, key1;  // Philox key: (source, seed)
+  uint32_t t_alpha;     // stop iff first Philox word < t_alpha
+  uint32_t pad;
+  double alpha;
+  double rmax;
+  double omega_unit;
+};
+
+struct QueryStatsDev {
+  u64 pushes;
+  u64 edge_ops;
+  u64 entries;
+  u64 walks;
+  u64 steps;
+  double r_sum;
+  int32_t rounds;
+  int32_t term_violations;
+};
+
+struct Ctrl {
+  u64 fr_cnt[2];       // frontier sizes, double-buffered by round parity
+  u64 entries;         // plan entries (all queries)
+  u64 walks;           // W (all queries)
+  u64 chunk_next;      // walk work queue cursor (in chunks)
+  u64 log_len;         // frontier log length (push-only path)
+  int32_t error;
+  int32_t pad;
+  u64 round_size[kMaxRoundsLogged];
+};
+
+struct GraphDev {
+  int32_t n;
+  int64_t m;
+  const int32_t* rowptr;
+  const int32_t* colidx;
+  const int2* info;
+  int32_t max_deg;
+};
+
+struct Layout {
+  size_t ctrl, qstats, queries, r, q, cnt, acc, pi;
+  size_t fr0, fr1, frx;
+  size_t plan_gi, plan_off, plan_wfx;
+  size_t tile_cnt, tile_walks, tile_eoff, tile_woff;
+  size_t hist, sel, cand_key, cand_id, cand_cnt, blk_ties;
+  size_t zero_begin, zero_end;
+  size_t total;
+  int64_t cap;  // frontier / plan capacity (batch * n)
+  int64_t tiles_per_row, plan_tiles, topk_blocks;
+};
+
+struct Ws {
+  Ctrl* ctrl;
+  QueryStatsDev* qstats;
+  QueryDev* queries;
+  float* r;
+  float* q;
+  uint32_t* cnt;
+  u64* acc;
+  float* pi;
+  u64* fr[2];
+  float* frx;
+  u64* plan_gi;
+  u64* plan_off;
+  u64* plan_wfx;
+  uint32_t* tile_cnt;
+  u64* tile_walks;
+  u64* tile_eoff;
+  u64* tile_woff;
+  uint32_t* hist;      // [batch][kHistBins]
+  uint32_t* sel;       // [batch][4]: prefix, remaining k, count above, pass
+  uint32_t* cand_key;  // [batch][FORA_MAX_K]
+  int32_t* cand_id;    // [batch][FORA_MAX_K]
+  uint32_t* cand_cnt;  // [batch]
+  uint32_t* blk_ties;  // [batch][topk_blocks]
+};
+
+Layout make_layout(int32_t n, int32_t batch);
+Ws carve(const Layout& L, void* base);
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two
+// 32x32->64 multiplies; key schedule bumps by the Weyl constants.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint32_t lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// floor(U * d / 2^64) for U = (hi << 32) | lo and d < 2^32: the part of the
+// 96-bit product above bit 64, from two 32x32->64 products.
+__device__ __forceinline__ uint32_t mul_shift_index(uint32_t hi, uint32_t lo, uint32_t d) {
+  const uint64_t a = (uint64_t)hi * d;
+  const uint64_t b = (uint64_t)lo * d;
+  return (uint32_t)((a + (b >> 32)) >> 32);
+}
+
+// ---- launchers (each enqueues on `s`; return hipError_t) -------------------
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_graph_check(const GraphDev& g, int* d_flags, int* d_maxdeg,
+                              int2* info, hipStream_t s);
+hipError_t launch_init_queries(const GraphDev& g, const Ws& w, int batch, hipStream_t s);
+hipError_t launch_push_round(const GraphDev& g, const Ws& w, int batch, int t,
+                             int blocks, bool stats, int32_t* frontier_log,
+                             int64_t log_cap, hipStream_t s);
+hipError_t launch_plan(const GraphDev& g, const Ws& w, const Layout& L, int batch,
+                       hipStream_t s);
+hipError_t launch_walks(const GraphDev& g, const Ws& w, int blocks, hipStream_t s);
+hipError_t launch_walk_plan_from_host(const GraphDev& g, const Ws& w, int64_t entries,
+                                      const int32_t* d_v, const uint64_t* d_omega,
+                                      const double* d_w, hipStream_t s);
+hipError_t launch_topk(const GraphDev& g, const Ws& w, const Layout& L, int batch,
+                       int kmax, int32_t* d_ids, float* d_vals, hipStream_t s);
+hipError_t launch_philox(int64_t count, const uint32_t* d_ctr, uint32_t k0, uint32_t k1,
+                         uint32_t* d_out, hipStream_t s);
+
+int device_cu_count();
+
+}  // namespace fora

@@ -1,0 +1,168 @@
+// Random walks with restart from the walk plan (Algorithm 2's walk loop).
+//
+// Walk g (a global id) belongs to plan entry e with plan_off[e] <= g <
+// plan_off[e+1]; it is walk j = g - plan_off[e] of start node v for query b.
+// Step s of the walk draws one Philox4x32-10 block with key (source, seed)
+// and counter (v, j, s, 0): it stops at the current node x if word 0 is
+// below floor(alpha * 2^32); otherwise it moves to out-neighbour
+// floor(U * d(x) / 2^64) of x, where U = word1 * 2^32 + word2. At its end
+// point t it adds 1 to cnt[t] and its entry's fixed-point weight to acc[t].
+//
+// Schedule: a persistent grid; each wavefront takes chunks of kWalkChunk
+// consecutive walk ids from a device work queue and keeps all 64 lanes busy:
+// a lane whose walk ends takes the next id of the chunk at once (ballot +
+// lane rank), so geometric walk lengths do not leave lanes idle. The entry of
+// a new id is found by a shuffle binary search over a 64-entry window of
+// plan offsets that the wave keeps in registers.
+#include "internal.h"
+#include "scan.h"
+
+namespace fora {
+
+constexpr int kWalkBlock = 256;
+
+// Largest e in [0, E) with off[e] <= target, by 64-way probing (wave-uniform).
+__device__ __forceinline__ u64 wave_find_entry(const u64* __restrict__ off, u64 E, u64 target) {
+  const int lane = threadIdx.x & 63;
+  u64 lo = 0, hi = E;  // off[lo] <= target (off[0] = 0); hi == E or off[hi] > target
+  while (hi - lo > 64) {
+    const u64 step = (hi - lo + 63) / 64;
+    const u64 p = lo + (u64)lane * step;
+    const bool ok = p < hi && off[p] <= target;
+    const u64 mask = __ballot(ok);
+    const int top = 63 - __builtin_clzll(mask);
+    lo = lo + (u64)top * step;
+    const u64 nh = lo + step;
+    hi = nh < hi ? nh : hi;
+  }
+  const u64 p = lo + (u64)lane;
+  const bool ok = p < hi && off[p] <= target;
+  const u64 mask = __ballot(ok);
+  return lo + (u64)(63 - __builtin_clzll(mask));
+}
+
+__global__ __launch_bounds__(kWalkBlock) void k_walks(
+    const u64* __restrict__ plan_gi, const u64* __restrict__ plan_off,
+    const u64* __restrict__ plan_wfx, Ctrl* ctrl, const QueryDev* __restrict__ Q,
+    QueryStatsDev* QS, const int2* __restrict__ info, const int32_t* __restrict__ colidx,
+    int n, uint32_t* __restrict__ cnt, u64* __restrict__ acc) {
+  if (ctrl->error) return;
+  const u64 W = ctrl->walks;
+  const u64 E = ctrl->entries;
+  const u64 nchunks = (W + kWalkChunk - 1) / kWalkChunk;
+  const int lane = threadIdx.x & 63;
+
+  bool active = false;
+  int b = 0;
+  uint32_t v = 0, j = 0, step = 0, k0 = 0, k1 = 0, ta = 0;
+  int32_t x = 0;
+  u64 wfx = 0;
+  int stat_b = -1;
+  u64 stat_steps = 0;
+
+  u64 cursor = 0, cend = 0, ebase = 0;
+  u64 woff = ~0ull;  // plan_off[ebase + lane], or all-ones past the end
+  bool more = true;
+
+  for (;;) {
+    const u64 free_mask = __ballot(!active);
+    if (free_mask != 0 && more) {
+      if (cursor >= cend) {
+        u64 c = 0;
+        if (lane == 0) c = atomicAdd(&ctrl->chunk_next, 1ull);
+        c = __shfl(c, 0, 64);
+        if (c >= nchunks) {
+          more = false;
+        } else {
+          cursor = c * (u64)kWalkChunk;
+          cend = cursor + kWalkChunk < W ? cursor + kWalkChunk : W;
+          ebase = wave_find_entry(plan_off, E, cursor);
+          woff = (ebase + lane <= E) ? plan_off[ebase + lane] : ~0ull;
+        }
+      }
+      if (more) {
+        // ids below the window's last offset map into the window
+        const u64 wlast = __shfl(woff, 63, 64);
+        const u64 limit = cend < wlast ? cend : wlast;
+        const u64 navail = limit - cursor;
+        const unsigned nfree = (unsigned)__popcll(free_mask);
+        const unsigned nassign = (u64)nfree < navail ? nfree : (unsigned)navail;
+        const unsigned rank = lane_rank(free_mask);
+        const u64 id = cursor + rank;
+        // largest L with woff_L <= id (all lanes run the search)
+        int lo = 0;
+#pragma unroll
+        for (int s = 32; s > 0; s >>= 1) {
+          const u64 o = __shfl(woff, lo + s, 64);
+          if (o <= id) lo += s;
+        }
+        const u64 o_lo = __shfl(woff, lo, 64);
+        if (!active && rank < nassign) {
+          const u64 e = ebase + (u64)lo;
+          const u64 gi = plan_gi[e];
+          wfx = plan_wfx[e];
+          b = (int)(gi >> 32);
+          v = (uint32_t)gi;
+          j = (uint32_t)(id - o_lo);
+          x = (int32_t)v;
+          step = 0;
+          k0 = Q[b].key0;
+          k1 = Q[b].key1;
+          ta = Q[b].t_alpha;
+          active = true;
+        }
+        cursor += nassign;
+        if (cursor < cend) {
+          int lc = 0;
+#pragma unroll
+          for (int s = 32; s > 0; s >>= 1) {
+            const u64 o = __shfl(woff, lc + s, 64);
+            if (o <= cursor) lc += s;
+          }
+          if (lc > 0) {
+            ebase += (u64)lc;
+            woff = (ebase + lane <= E) ? plan_off[ebase + lane] : ~0ull;
+          }
+        }
+      }
+    }
+    if (!__any(active)) {
+      if (!more) break;
+      continue;
+    }
+    if (active) {
+      const uint4 y = philox4x32_10(make_uint4(v, j, step, 0u), k0, k1);
+      if (y.x < ta) {
+        const size_t t = (size_t)b * n + x;
+        atomicAdd(&cnt[t], 1u);
+        atomicAdd(&acc[t], wfx);
+        if (b != stat_b) {
+          if (stat_b >= 0) atomicAdd(&QS[stat_b].steps, stat_steps);
+          stat_b = b;
+          stat_steps = 0;
+        }
+        stat_steps += step;
+        active = false;
+      } else {
+        const int2 inf = info[x];
+        const uint32_t idx = mul_shift_index(y.y, y.z, (uint32_t)inf.y);
+        x = colidx[(int64_t)inf.x + idx];
+        ++step;
+      }
+    }
+  }
+  // per-query step totals: one atomic per wave when the wave saw one query
+  const int b0 = __shfl(stat_b, 0, 64);
+  const u64 mine = (stat_b == b0) ? stat_steps : 0ull;
+  const u64 sum = wave_sum(mine);
+  if (lane == 0 && b0 >= 0) atomicAdd(&QS[b0].steps, sum);
+  if (stat_b != b0 && stat_b >= 0) atomicAdd(&QS[stat_b].steps, stat_steps);
+}
+
+hipError_t launch_walks(const GraphDev& g, const Ws& w, int blocks, hipStream_t s) {
+  k_walks<<<blocks, kWalkBlock, 0, s>>>(w.plan_gi, w.plan_off, w.plan_wfx, w.ctrl, w.queries,
+                                        w.qstats, g.info, g.colidx, g.n, w.cnt, w.acc);
+  return hipGetLastError();
+}
+
+}  // namespace fora

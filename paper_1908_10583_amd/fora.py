@@ -1,0 +1,297 @@
+"""Python binding of the FORA HIP library (``libfora.so``).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels. PyTorch provides device memory and streams. The functions keep
+the C ABI's names (``fora_build_csr``, ``fora_ssppr``, ``fora_ssppr_batch``,
+...). If the library is not built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfora.so")
+
+FORA_OK, FORA_E_ARG, FORA_E_GRAPH, FORA_E_NOMEM, FORA_E_HIP, FORA_E_OVERFLOW = 0, -1, -2, -3, -4, -5
+FORA_MAX_K = 4096
+FORA_MAX_BATCH = 4096
+
+
+class FORAError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"FORA error {code}: {msg}")
+        self.code = code
+
+
+class fora_stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("term_violations", ctypes.c_int32),
+                ("pushes", ctypes.c_int64), ("edge_ops", ctypes.c_int64),
+                ("plan_entries", ctypes.c_int64), ("walks", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64), ("r_sum", ctypes.c_double),
+                ("rmax", ctypes.c_double), ("omega_unit", ctypes.c_double),
+                ("t_alpha", ctypes.c_uint32), ("ms_push", ctypes.c_float),
+                ("ms_plan", ctypes.c_float), ("ms_walk", ctypes.c_float),
+                ("ms_topk", ctypes.c_float), ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class fora_query(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_int32), ("k", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("eps", ctypes.c_double), ("delta", ctypes.c_double), ("pf", ctypes.c_double),
+                ("rmax", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class fora_views(ctypes.Structure):
+    _fields_ = [("residue", ctypes.c_void_p), ("reserve", ctypes.c_void_p),
+                ("walk_count", ctypes.c_void_p), ("walk_weight_fx", ctypes.c_void_p),
+                ("pi_hat", ctypes.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32, U64, F64, SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                      ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double,
+                                      ctypes.c_size_t)
+    sig = {
+        "fora_last_error": ([], ctypes.c_char_p),
+        "fora_build_csr": ([I32, I64, P, P, P, ctypes.POINTER(P)], ctypes.c_int),
+        "fora_free_graph": ([P], ctypes.c_int),
+        "fora_graph_info": ([P, ctypes.POINTER(I32), ctypes.POINTER(I64), ctypes.POINTER(I32)],
+                            ctypes.c_int),
+        "fora_workspace_size": ([P, I32, ctypes.POINTER(SZ)], ctypes.c_int),
+        "fora_workspace_views": ([P, I32, P, ctypes.POINTER(fora_views)], ctypes.c_int),
+        "fora_ssppr": ([P, I32, F64, F64, F64, F64, I32, F64, U64, P, SZ, P, P,
+                        ctypes.POINTER(fora_stats), P], ctypes.c_int),
+        "fora_ssppr_batch": ([P, I32, ctypes.POINTER(fora_query), I32, P, SZ, P, P,
+                              ctypes.POINTER(fora_stats), P], ctypes.c_int),
+        "fora_push_only": ([P, I32, F64, F64, P, SZ, I32, P, P, I64,
+                            ctypes.POINTER(fora_stats), P], ctypes.c_int),
+        "fora_walk_only": ([P, I64, P, P, P, U32, U32, F64, P, SZ, ctypes.POINTER(U64), P],
+                           ctypes.c_int),
+        "fora_philox": ([I64, P, U32, U32, P, P], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+
+EXPORTED = ["fora_last_error", "fora_build_csr", "fora_free_graph", "fora_graph_info",
+            "fora_workspace_size", "fora_workspace_views", "fora_ssppr", "fora_ssppr_batch",
+            "fora_push_only", "fora_walk_only", "fora_philox"]
+
+
+def _check(rc: int):
+    if rc != FORA_OK:
+        raise FORAError(rc, _lib.fora_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Graph:
+    """A validated CSR graph on the device (``fora_build_csr``). Keeps the CSR
+    tensors alive for as long as the handle lives."""
+
+    def __init__(self, rowptr: torch.Tensor, colidx: torch.Tensor, stream=None):
+        if rowptr.dtype != torch.int32 or colidx.dtype != torch.int32:
+            raise TypeError("rowptr and colidx must be int32")
+        if not (rowptr.is_cuda and colidx.is_cuda):
+            raise TypeError("rowptr and colidx must be device tensors")
+        self.rowptr = rowptr.contiguous()
+        self.colidx = colidx.contiguous()
+        self.n = int(self.rowptr.numel() - 1)
+        self.m = int(self.colidx.numel())
+        self.device = self.rowptr.device
+        h = ctypes.c_void_p()
+        _check(_lib.fora_build_csr(self.n, self.m, _ptr(self.rowptr), _ptr(self.colidx),
+                                   ctypes.c_void_p(_stream(stream)), ctypes.byref(h)))
+        self.handle = h
+        n = ctypes.c_int32()
+        m = ctypes.c_int64()
+        md = ctypes.c_int32()
+        _check(_lib.fora_graph_info(self.handle, ctypes.byref(n), ctypes.byref(m),
+                                    ctypes.byref(md)))
+        self.max_degree = md.value
+
+    @classmethod
+    def from_numpy(cls, rowptr: np.ndarray, colidx: np.ndarray, device="cuda"):
+        return cls(torch.from_numpy(np.ascontiguousarray(rowptr, np.int32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(colidx, np.int32)).to(device))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            _lib.fora_free_graph(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fora_workspace_size(g: Graph, batch: int) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.fora_workspace_size(g.handle, batch, ctypes.byref(out)))
+    return out.value
+
+
+def workspace(g: Graph, batch: int = 1) -> torch.Tensor:
+    """A device byte tensor large enough for ``batch`` queries."""
+    return torch.empty(fora_workspace_size(g, batch), dtype=torch.uint8, device=g.device)
+
+
+def fora_workspace_views(g: Graph, batch: int, ws: torch.Tensor) -> dict:
+    """Tensors aliasing the dense per-query arrays inside ``ws`` (rows of n)."""
+    v = fora_views()
+    _check(_lib.fora_workspace_views(g.handle, batch, _ptr(ws), ctypes.byref(v)))
+    base = ws.data_ptr()
+    cap = batch * g.n
+
+    def view(p, dtype, itemsize):
+        off = p - base
+        return ws[off:off + cap * itemsize].view(dtype).view(batch, g.n)
+
+    return dict(residue=view(v.residue, torch.float32, 4),
+                reserve=view(v.reserve, torch.float32, 4),
+                walk_count=view(v.walk_count, torch.int32, 4),        # uint32 bits
+                walk_weight_fx=view(v.walk_weight_fx, torch.int64, 8),  # uint64 bits
+                pi_hat=view(v.pi_hat, torch.float32, 4))
+
+
+@dataclass
+class Result:
+    ids: torch.Tensor
+    vals: torch.Tensor
+    stats: list | dict | None
+
+
+def fora_ssppr(g: Graph, src: int, alpha: float = 0.2, eps: float = 0.5,
+               delta: float | None = None, pf: float | None = None, k: int = 500,
+               rmax: float | None = None, seed: int = 0, ws: torch.Tensor | None = None,
+               stats: bool = False, out: tuple | None = None, stream=None) -> Result:
+    delta = 1.0 / g.n if delta is None else delta
+    pf = 1.0 / g.n if pf is None else pf
+    ws = workspace(g, 1) if ws is None else ws
+    if out is None:
+        ids = torch.empty(k, dtype=torch.int32, device=g.device)
+        vals = torch.empty(k, dtype=torch.float32, device=g.device)
+    else:
+        ids, vals = out
+    st = fora_stats() if stats else None
+    _check(_lib.fora_ssppr(g.handle, int(src), alpha, eps, delta, pf, int(k),
+                           0.0 if rmax is None else float(rmax), int(seed) & (2**64 - 1),
+                           _ptr(ws), ws.numel(), _ptr(ids), _ptr(vals),
+                           ctypes.byref(st) if st is not None else None,
+                           ctypes.c_void_p(_stream(stream))))
+    return Result(ids, vals, st.as_dict() if st is not None else None)
+
+
+def make_queries(srcs, alpha=0.2, eps=0.5, delta=None, pf=None, k=500, rmax=None, seed=0,
+                 n: int | None = None):
+    """An array of ``fora_query`` (scalars broadcast; lists give per-query values)."""
+    srcs = list(np.asarray(srcs).reshape(-1))
+    B = len(srcs)
+
+    def per(x, default=None):
+        if x is None:
+            return [default] * B
+        if np.ndim(x) == 0:
+            return [x] * B
+        x = list(np.asarray(x).reshape(-1))
+        assert len(x) == B
+        return x
+
+    delta = per(delta, None if n is None else 1.0 / n)
+    pf = per(pf, None if n is None else 1.0 / n)
+    arr = (fora_query * B)()
+    for i, (s, a, e, d, p, kk, r, sd) in enumerate(zip(srcs, per(alpha), per(eps), delta, pf,
+                                                       per(k), per(rmax, 0.0), per(seed))):
+        arr[i].src, arr[i].k = int(s), int(kk)
+        arr[i].alpha, arr[i].eps = float(a), float(e)
+        arr[i].delta, arr[i].pf = float(d), float(p)
+        arr[i].rmax = 0.0 if r is None else float(r)
+        arr[i].seed = int(sd) & (2**64 - 1)
+    return arr
+
+
+def fora_ssppr_batch(g: Graph, queries, kmax: int | None = None,
+                     ws: torch.Tensor | None = None, stats: bool = False,
+                     out: tuple | None = None, stream=None) -> Result:
+    B = len(queries)
+    kmax = max(q.k for q in queries) if kmax is None else kmax
+    ws = workspace(g, B) if ws is None else ws
+    if out is None:
+        ids = torch.empty((B, kmax), dtype=torch.int32, device=g.device)
+        vals = torch.empty((B, kmax), dtype=torch.float32, device=g.device)
+    else:
+        ids, vals = out
+    st = (fora_stats * B)() if stats else None
+    _check(_lib.fora_ssppr_batch(g.handle, B, queries, kmax, _ptr(ws), ws.numel(), _ptr(ids),
+                                 _ptr(vals), st, ctypes.c_void_p(_stream(stream))))
+    return Result(ids, vals, [s.as_dict() for s in st] if st is not None else None)
+
+
+def fora_push_only(g: Graph, src: int, alpha: float, rmax: float,
+                   ws: torch.Tensor | None = None, max_rounds: int = 4096,
+                   log_frontiers: bool = False, frontier_cap: int | None = None, stream=None):
+    ws = workspace(g, 1) if ws is None else ws
+    sizes = np.zeros(max_rounds, np.int32)
+    cap = frontier_cap if frontier_cap is not None else 64 * g.n
+    flog = torch.empty(cap, dtype=torch.int32, device=g.device) if log_frontiers else None
+    st = fora_stats()
+    _check(_lib.fora_push_only(g.handle, int(src), alpha, rmax, _ptr(ws), ws.numel(),
+                               max_rounds, sizes.ctypes.data_as(ctypes.c_void_p), _ptr(flog),
+                               cap if log_frontiers else 0, ctypes.byref(st),
+                               ctypes.c_void_p(_stream(stream))))
+    v = fora_workspace_views(g, 1, ws)
+    out = dict(r=v["residue"][0], q=v["reserve"][0], stats=st.as_dict(),
+               round_sizes=sizes[:st.rounds].copy())
+    if log_frontiers:
+        offs = np.concatenate([[0], np.cumsum(out["round_sizes"])])
+        host = flog[:int(offs[-1])].cpu().numpy()
+        out["frontiers"] = [np.sort(host[offs[i]:offs[i + 1]]) for i in range(st.rounds)]
+    return out
+
+
+def fora_walk_only(g: Graph, plan_v, plan_omega, plan_w, key0: int, key1: int,
+                   alpha: float, ws: torch.Tensor | None = None, stream=None):
+    ws = workspace(g, 1) if ws is None else ws
+    dv = torch.as_tensor(np.ascontiguousarray(plan_v, np.int32)).to(g.device)
+    do = torch.as_tensor(np.ascontiguousarray(plan_omega, np.uint64).view(np.int64)).to(g.device)
+    dw = torch.as_tensor(np.ascontiguousarray(plan_w, np.float64)).to(g.device)
+    steps = ctypes.c_uint64()
+    _check(_lib.fora_walk_only(g.handle, int(dv.numel()), _ptr(dv), _ptr(do), _ptr(dw),
+                               key0 & 0xFFFFFFFF, key1 & 0xFFFFFFFF, alpha, _ptr(ws),
+                               ws.numel(), ctypes.byref(steps), ctypes.c_void_p(_stream(stream))))
+    v = fora_workspace_views(g, 1, ws)
+    return dict(cnt=v["walk_count"][0], acc_fx=v["walk_weight_fx"][0], steps=steps.value)
+
+
+def fora_philox(ctr: np.ndarray, key, device="cuda", stream=None) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, np.uint32).reshape(-1, 4)
+    dc = torch.as_tensor(c.view(np.int32)).to(device)
+    out = torch.empty_like(dc)
+    _check(_lib.fora_philox(c.shape[0], _ptr(dc), int(key[0]) & 0xFFFFFFFF,
+                            int(key[1]) & 0xFFFFFFFF, _ptr(out), ctypes.c_void_p(_stream(stream))))
+    return out.cpu().numpy().view(np.uint32)

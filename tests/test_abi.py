@@ -1,0 +1,51 @@
+"""The C-ABI library loads on the CPU and exports every symbol the header
+declares; the Python binding wraps each of them. No GPU calls."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1908_10583_amd", "libfora.so")
+HEADER = os.path.join(ROOT, "include", "fora.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fora_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("fora_build_csr", "fora_ssppr", "fora_ssppr_batch", "fora_workspace_size",
+                 "fora_last_error"):
+        assert must in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfora.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfora.so not built")
+def test_binding_wraps_every_symbol():
+    from paper_1908_10583_amd import fora
+    assert sorted(fora.EXPORTED) == declared_functions()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfora.so not built")
+def test_argument_errors_need_no_gpu():
+    # argument checks run on the host before any device work
+    from paper_1908_10583_amd import fora
+    lib = fora._lib
+    out = ctypes.c_void_p()
+    assert lib.fora_build_csr(0, 0, None, None, None, ctypes.byref(out)) == fora.FORA_E_ARG
+    assert b"n must be" in lib.fora_last_error()
+    assert lib.fora_build_csr(10, 2**31, ctypes.c_void_p(8), ctypes.c_void_p(8), None,
+                              ctypes.byref(out)) == fora.FORA_E_ARG
+    sz = ctypes.c_size_t()
+    assert lib.fora_workspace_size(None, 1, ctypes.byref(sz)) == fora.FORA_E_ARG

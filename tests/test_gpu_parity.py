@@ -1,0 +1,289 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars (from the method's arithmetic):
+* integer outputs (walk end-point counts, step totals, frontier sets, top-k
+  ids of a given estimate) are bit-exact;
+* FP32 residue / reserve vs the FP64 oracle: |g - o| <= 1e-5 |o| + 1e-12;
+* walk weights: the GPU sums round(w * 2^62) per walk in integers, so it may
+  differ from the FP64 sum by at most cnt * 2^-63 plus FP64 rounding.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.graphs import Graph
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1908_10583_amd import fora  # noqa: E402  (fails loudly if not built)
+
+ALPHA = 0.2
+RTOL, ATOL = 1e-5, 1e-12
+
+
+def close(g, o, rtol=RTOL, atol=ATOL):
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    return np.abs(g - o) <= rtol * np.abs(o) + atol
+
+
+@pytest.fixture(scope="module")
+def g1k():
+    return synth.uniform_out_graph(1000, 10, seed=1)
+
+
+@pytest.fixture(scope="module")
+def G1k(g1k):
+    return fora.Graph.from_numpy(g1k.rowptr, g1k.colidx)
+
+
+@pytest.fixture(scope="module")
+def grmat12():
+    return synth.rmat_graph(12, seed=12, cache=False)
+
+
+@pytest.fixture(scope="module")
+def Grmat12(grmat12):
+    return fora.Graph.from_numpy(grmat12.rowptr, grmat12.colidx)
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+# ------------------------------------------------------------------ RNG
+def test_philox_bit_exact():
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2**32, size=(100003, 4), dtype=np.uint64).astype(np.uint32)
+    for key in ([0, 0], [123, 456], [0xFFFFFFFF, 0x9E3779B9]):
+        got = fora.fora_philox(ctr, key)
+        want = oracle.philox(ctr, key)
+        assert np.array_equal(got, want)
+
+
+# ------------------------------------------------------------------ graph ingest
+def test_build_csr_rejects_malformed():
+    dev = "cuda"
+    cases = [
+        ([0, 1, 1], [1], fora.FORA_E_GRAPH),           # node 1 has no out-edge
+        ([0, 1, 2], [1, 2], fora.FORA_E_GRAPH),        # target out of range
+        ([0, 2, 1], [1], fora.FORA_E_GRAPH),           # rowptr decreasing / rowptr[n] != m
+        ([1, 1, 2], [0, 1], fora.FORA_E_GRAPH),        # rowptr[0] != 0
+    ]
+    for rp, ci, code in cases:
+        with pytest.raises(fora.FORAError) as ei:
+            fora.Graph(torch.tensor(rp, dtype=torch.int32, device=dev),
+                       torch.tensor(ci, dtype=torch.int32, device=dev))
+        assert ei.value.code == code
+    G = fora.Graph(torch.tensor([0, 1, 2], dtype=torch.int32, device=dev),
+                   torch.tensor([1, 0], dtype=torch.int32, device=dev))
+    assert G.max_degree == 1
+
+
+def test_argument_checks(G1k):
+    ws = fora.workspace(G1k, 1)
+    bad = [dict(src=-1), dict(src=1000), dict(alpha=0.0), dict(alpha=1.0), dict(eps=0.0),
+           dict(eps=1.0), dict(delta=0.0), dict(pf=1.0), dict(k=0), dict(k=1001)]
+    for b in bad:
+        kw = dict(src=0, alpha=0.2, eps=0.5, delta=1e-3, pf=1e-3, k=50)
+        kw.update(b)
+        k = max(kw["k"], 1)
+        with pytest.raises(fora.FORAError) as ei:
+            fora.fora_ssppr(G1k, kw["src"], kw["alpha"], kw["eps"], kw["delta"], kw["pf"],
+                            kw["k"], ws=ws,
+                            out=(torch.empty(k, dtype=torch.int32, device="cuda"),
+                                 torch.empty(k, dtype=torch.float32, device="cuda")))
+        assert ei.value.code == fora.FORA_E_ARG
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(fora.FORAError) as ei:
+        fora.fora_ssppr(G1k, 0, k=50, ws=small)
+    assert ei.value.code == fora.FORA_E_NOMEM
+
+
+# ------------------------------------------------------------------ push
+def _push_compare(g, G, s, rmax):
+    ref = oracle.push(g, s, ALPHA, rmax, log_frontiers=True)
+    got = fora.fora_push_only(G, s, ALPHA, rmax, log_frontiers=True)
+    return ref, got
+
+
+def test_push_golden_tiny():
+    import json, os
+    from conftest import GOLDEN
+    gold = json.load(open(os.path.join(GOLDEN, "push_sync_tiny.json")))
+    gr = gold["graph"]
+    G = fora.Graph.from_numpy(np.array(gr["rowptr"]), np.array(gr["colidx"]))
+    got = fora.fora_push_only(G, gold["source"], gold["alpha"], gold["rmax"], log_frontiers=True)
+    assert got["stats"]["rounds"] == gold["rounds"]
+    assert [list(f) for f in got["frontiers"]] == gold["frontiers"]
+    assert np.all(close(got["q"].cpu().numpy(), gold["reserve"], rtol=1e-6))
+    assert np.all(close(got["r"].cpu().numpy(), gold["residue"], rtol=1e-6))
+
+
+@pytest.mark.parametrize("s", [0, 17, 999])
+@pytest.mark.parametrize("rmax", [3.754e-5, 1e-3, 1e-6])
+def test_push_parity_uniform(g1k, G1k, s, rmax):
+    ref, got = _push_compare(g1k, G1k, s, rmax)
+    # FP32 accumulation can flip only a test within ~1e-6 of its threshold
+    assert ref["min_margin"] > 1e-5, "a residue sits on its threshold; pick another case"
+    assert got["stats"]["rounds"] == ref["rounds"]
+    assert np.array_equal(got["round_sizes"], ref["round_sizes"])
+    for fg, fo in zip(got["frontiers"], ref["frontiers"]):
+        assert np.array_equal(fg, fo)
+    assert np.all(close(got["q"].cpu().numpy(), ref["q"]))
+    assert np.all(close(got["r"].cpu().numpy(), ref["r"]))
+    assert got["stats"]["edge_ops"] == ref["edge_ops"]
+    assert got["stats"]["term_violations"] == 0
+
+
+def test_push_parity_rmat_ragged(grmat12, Grmat12):
+    deg = grmat12.degrees()
+    for s in (int(np.argmax(deg)), 3, 4095):
+        ref, got = _push_compare(grmat12, Grmat12, s, 1e-6)
+        if ref["min_margin"] <= 1e-5:
+            continue
+        assert np.array_equal(got["round_sizes"], ref["round_sizes"])
+        assert np.all(close(got["q"].cpu().numpy(), ref["q"]))
+        assert np.all(close(got["r"].cpu().numpy(), ref["r"]))
+
+
+# ------------------------------------------------------------------ walks
+def _walk_compare(g, G, pv, po, pw, key0, key1):
+    t_alpha = oracle.constants(g.m, ALPHA, 0.5, 0.01, 0.01)["t_alpha"]
+    ref = oracle.walks(g, key0, key1, t_alpha, pv, po, pw)
+    got = fora.fora_walk_only(G, pv, po, pw, key0, key1, ALPHA)
+    cnt = _u32(got["cnt"]).astype(np.uint64)
+    assert np.array_equal(cnt, ref["cnt"])
+    assert got["steps"] == ref["steps"]
+    acc = _u64(got["acc_fx"]).astype(np.float64) / 2.0**62
+    tol = ref["cnt"] * 2.0**-62 + 1e-15 * ref["acc"]
+    assert np.all(np.abs(acc - ref["acc"]) <= tol)
+    return ref, got
+
+
+def test_walk_parity_oracle_plan(g1k, G1k):
+    c = oracle.constants(g1k.m, ALPHA, 0.5, 1e-3, 1e-3)
+    ps = oracle.push(g1k, 0, ALPHA, c["rmax"])
+    pv, po, pw = oracle.plan(ps["r"], c["omega_unit"])
+    _walk_compare(g1k, G1k, pv, po, pw, 0, 7)
+
+
+@pytest.mark.parametrize("entries,max_walks,seed", [(1, 1, 0), (1, 100000, 1), (7, 3, 2),
+                                                    (4096, 1, 3), (3000, 300, 4),
+                                                    (64, 513, 5), (1000, 2000, 6)])
+def test_walk_parity_random_plans(grmat12, Grmat12, entries, max_walks, seed):
+    pv, po, pw = synth.random_walk_plan(grmat12, entries, max_walks, seed)
+    _walk_compare(grmat12, Grmat12, pv, po, pw, 11 + seed, 99)
+
+
+def test_walk_only_empty_plan(G1k):
+    got = fora.fora_walk_only(G1k, np.zeros(0, np.int32), np.zeros(0, np.uint64),
+                              np.zeros(0), 0, 0, ALPHA)
+    assert got["steps"] == 0
+    assert int(_u32(got["cnt"]).sum()) == 0
+
+
+# ------------------------------------------------------------------ end to end
+def _e2e(g, G, s, k, seed, rmax=None, eps=0.5):
+    ref = oracle.fora(g, s, alpha=ALPHA, eps=eps, k=k, seed=seed, rmax=rmax)
+    ws = fora.workspace(G, 1)
+    res = fora.fora_ssppr(G, s, alpha=ALPHA, eps=eps, k=k, seed=seed, rmax=rmax, ws=ws,
+                          stats=True)
+    return ref, res, fora.fora_workspace_views(G, 1, ws)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_end_to_end_uniform(g1k, G1k, seed):
+    ref, res, v = _e2e(g1k, G1k, 0, 50, seed)
+    st = res.stats
+    assert st["omega_unit"] == ref["consts"]["omega_unit"]
+    assert st["rmax"] == ref["consts"]["rmax"]
+    assert st["t_alpha"] == ref["consts"]["t_alpha"]
+    assert st["rounds"] == ref["rounds"] and st["term_violations"] == 0
+    assert np.all(close(v["reserve"][0].cpu().numpy(), ref["q"]))
+    assert np.all(close(v["residue"][0].cpu().numpy(), ref["r"]))
+    # the walk plan is a function of the residues: same omega_v => same walks
+    r_gpu = v["residue"][0].cpu().numpy().astype(np.float64)
+    om_gpu = np.ceil(r_gpu * st["omega_unit"])
+    om_ref = np.zeros(g1k.n)
+    om_ref[ref["plan"][0]] = ref["plan"][1]
+    if np.array_equal(om_gpu, om_ref):
+        assert st["walks"] == ref["walks"] and st["steps"] == ref["steps"]
+        assert np.array_equal(_u32(v["walk_count"][0]).astype(np.uint64), ref["cnt"])
+    pi = v["pi_hat"][0].cpu().numpy()
+    assert np.all(close(pi, ref["pi"], rtol=2e-5, atol=1e-9))
+    assert abs(pi.astype(np.float64).sum() - 1.0) < 1e-4
+    ids = res.ids.cpu().numpy()
+    vals = res.vals.cpu().numpy()
+    # top-k of the GPU's own estimate is exact (a sort decides it)
+    order = np.lexsort((np.arange(g1k.n), -pi))[:50]
+    assert np.array_equal(ids, order)
+    assert np.array_equal(vals, pi[order])
+    # against the oracle: differences only between near-ties
+    kth = ref["topk_vals"][-1]
+    diff = set(ids.tolist()) ^ set(ref["topk_ids"].tolist())
+    for t in diff:
+        assert abs(ref["pi"][t] - kth) <= 2e-5 * kth + 1e-9
+
+
+def test_end_to_end_monte_carlo_case(g1k, G1k):
+    ref, res, v = _e2e(g1k, G1k, 0, 50, 5, rmax=1.0)
+    assert res.stats["rounds"] == 0 and ref["rounds"] == 0
+    assert res.stats["walks"] == ref["walks"] == math.ceil(ref["consts"]["omega_unit"])
+    assert res.stats["steps"] == ref["steps"]
+    assert np.array_equal(_u32(v["walk_count"][0]).astype(np.uint64), ref["cnt"])
+
+
+@pytest.mark.parametrize("k", [1, 7, 500, 1000])
+def test_topk_sizes(g1k, G1k, k):
+    res = fora.fora_ssppr(G1k, 3, k=k, seed=9, delta=1e-3, pf=1e-3)
+    ws_pi = None
+    ids = res.ids.cpu().numpy()
+    assert len(set(ids.tolist())) == k
+    vals = res.vals.cpu().numpy()
+    assert np.all(np.diff(vals) <= 0)
+    del ws_pi
+
+
+def test_tiny_graph_self_loop_and_full_k():
+    # n = 1 with a self-loop; and a 2-node cycle with k = n (padding rules)
+    G = fora.Graph.from_numpy(np.array([0, 1]), np.array([0]))
+    res = fora.fora_ssppr(G, 0, k=1, seed=0, delta=0.5, pf=0.5)
+    assert res.ids.cpu().tolist() == [0]
+    assert abs(float(res.vals.cpu()[0]) - 1.0) < 1e-6
+    G2 = fora.Graph.from_numpy(np.array([0, 1, 2]), np.array([1, 0]))
+    res = fora.fora_ssppr(G2, 1, k=2, seed=0, delta=0.5, pf=0.5)
+    assert sorted(res.ids.cpu().tolist()) == [0, 1]
+
+
+# ------------------------------------------------------------------ batch
+def test_batch_matches_single(g1k, G1k):
+    srcs = [0, 5, 5, 999, 123]
+    seeds = [1, 2, 2, 3, 4]
+    qs = fora.make_queries(srcs, k=50, seed=seeds, n=g1k.n)
+    ws = fora.workspace(G1k, len(srcs))
+    out = fora.fora_ssppr_batch(G1k, qs, ws=ws, stats=True)
+    vb = fora.fora_workspace_views(G1k, len(srcs), ws)
+    for i, (s, sd) in enumerate(zip(srcs, seeds)):
+        ref = oracle.fora(g1k, s, k=50, seed=sd)
+        st = out.stats[i]
+        assert st["rounds"] == ref["rounds"]
+        assert np.all(close(vb["reserve"][i].cpu().numpy(), ref["q"]))
+        assert np.all(close(vb["residue"][i].cpu().numpy(), ref["r"]))
+        pi = vb["pi_hat"][i].cpu().numpy()
+        assert np.all(close(pi, ref["pi"], rtol=2e-5, atol=1e-9))
+        order = np.lexsort((np.arange(g1k.n), -pi))[:50]
+        assert np.array_equal(out.ids[i].cpu().numpy(), order)
+    # duplicates give identical walks
+    assert np.array_equal(vb["walk_count"][1].cpu().numpy(), vb["walk_count"][2].cpu().numpy())
