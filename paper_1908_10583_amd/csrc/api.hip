@@ -13,7 +13,7 @@
 struct fora_graph {
   fora::GraphDev dev;
   int2* info_owned = nullptr;
-  int* flags_owned = nullptr;  // 2 ints: check flags, max degree
+  int* flags_owned = nullptr;  // 3 ints: check flags, max degree, hub count
   int device = 0;
   int cus = 256;
   // pinned host slots for the small read-backs of the push loop
@@ -121,7 +121,7 @@ int prepare(const fora_graph* g, int batch, void* d_ws, size_t ws_bytes, Call& c
   if (batch < 1 || batch > FORA_MAX_BATCH) return fail(FORA_E_ARG, "batch out of range");
   if (!d_ws) return fail(FORA_E_ARG, "null workspace");
   if (((uintptr_t)d_ws & 255) != 0) return fail(FORA_E_ARG, "workspace must be 256-byte aligned");
-  c.L = make_layout(g->dev.n, batch);
+  c.L = make_layout(g->dev, batch);
   if (ws_bytes < c.L.total) return fail(FORA_E_NOMEM, "workspace too small");
   c.w = carve(c.L, d_ws);
   return FORA_OK;
@@ -136,7 +136,8 @@ int run_push(fora_graph* g, const Call& c, int batch, hipStream_t s, bool stats,
   int t = 0, group = 4;
   for (;;) {
     for (int i = 0; i < group; ++i, ++t)
-      FORA_HIP(launch_push_round(g->dev, c.w, batch, t, push_blocks(g), stats, log, log_cap, s));
+      FORA_HIP(launch_push_round(g->dev, c.w, c.L, batch, t, push_blocks(g), stats, log,
+                                 log_cap, s));
     FORA_HIP(hipMemcpyAsync(ps.p, &c.w.ctrl->fr_cnt[t & 1], sizeof(uint64_t),
                             hipMemcpyDeviceToHost, s));
     FORA_HIP(hipStreamSynchronize(s));
@@ -178,10 +179,10 @@ int finish(fora_graph* g, const Call& c, int batch, hipStream_t s, fora_stats* h
            const std::vector<QueryDev>& qd, const PhaseEvents* pe = nullptr) {
   int flags = 0;
   FORA_HIP(hipMemcpyAsync(&flags, &c.w.ctrl->error, sizeof(int), hipMemcpyDeviceToHost, s));
-  std::vector<QueryStatsDev> qs;
+  std::vector<StatSlot> slots;
   if (h_stats) {
-    qs.resize(batch);
-    FORA_HIP(hipMemcpyAsync(qs.data(), c.w.qstats, sizeof(QueryStatsDev) * batch,
+    slots.resize((size_t)batch * kStatSlots);
+    FORA_HIP(hipMemcpyAsync(slots.data(), c.w.qstats, sizeof(StatSlot) * slots.size(),
                             hipMemcpyDeviceToHost, s));
   }
   FORA_HIP(hipStreamSynchronize(s));
@@ -191,14 +192,17 @@ int finish(fora_graph* g, const Call& c, int batch, hipStream_t s, fora_stats* h
     for (int b = 0; b < batch; ++b) {
       fora_stats& o = h_stats[b];
       std::memset(&o, 0, sizeof(o));
-      o.rounds = qs[b].rounds;
-      o.term_violations = qs[b].term_violations;
-      o.pushes = (int64_t)qs[b].pushes;
-      o.edge_ops = (int64_t)qs[b].edge_ops;
-      o.plan_entries = (int64_t)qs[b].entries;
-      o.walks = qs[b].walks;
-      o.steps = qs[b].steps;
-      o.r_sum = qs[b].r_sum;
+      for (int k = 0; k < kStatSlots; ++k) {
+        const StatSlot& q = slots[(size_t)b * kStatSlots + k];
+        o.rounds = std::max(o.rounds, q.rounds);
+        o.term_violations += q.term_violations;
+        o.pushes += (int64_t)q.pushes;
+        o.edge_ops += (int64_t)q.edge_ops;
+        o.plan_entries += (int64_t)q.entries;
+        o.walks += q.walks;
+        o.steps += q.steps;
+        o.r_sum += q.r_sum;
+      }
       o.rmax = qd[b].rmax;
       o.omega_unit = qd[b].omega_unit;
       o.t_alpha = qd[b].t_alpha;
@@ -250,7 +254,8 @@ int run_queries(fora_graph* g, int batch, const fora_query* qs, int kmax, void* 
 
 }  // namespace
 
-Layout make_layout(int32_t n, int32_t batch) {
+Layout make_layout(const GraphDev& g, int32_t batch) {
+  const int32_t n = g.n;
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -261,13 +266,14 @@ Layout make_layout(int32_t n, int32_t batch) {
   };
   const size_t cap = (size_t)batch * (size_t)n;
   L.cap = (int64_t)cap;
+  L.hub_cap = (int64_t)batch * (int64_t)std::max(g.n_hubs, 1);
   L.tiles_per_row = (n + kPlanTile - 1) / kPlanTile;
   L.plan_tiles = L.tiles_per_row * batch;
   L.topk_blocks = (n + kTopkTile - 1) / kTopkTile;
   // region cleared at the start of every call
   L.ctrl = take(sizeof(Ctrl));
   L.zero_begin = L.ctrl;
-  L.qstats = take(sizeof(QueryStatsDev) * batch);
+  L.qstats = take(sizeof(StatSlot) * (size_t)kStatSlots * batch);
   L.r = take(4 * cap);
   L.q = take(4 * cap);
   L.cnt = take(4 * cap);
@@ -281,6 +287,8 @@ Layout make_layout(int32_t n, int32_t batch) {
   L.fr0 = take(8 * cap);
   L.fr1 = take(8 * cap);
   L.frx = take(4 * cap);
+  L.hub_idx = take(8 * (size_t)L.hub_cap);
+  L.hub_base = take(8 * (size_t)L.hub_cap);
   L.plan_gi = take(8 * cap);
   L.plan_off = take(8 * (cap + 1));
   L.plan_wfx = take(8 * cap);
@@ -310,6 +318,8 @@ Ws carve(const Layout& L, void* base) {
   w.fr[0] = (u64*)(p + L.fr0);
   w.fr[1] = (u64*)(p + L.fr1);
   w.frx = (float*)(p + L.frx);
+  w.hub_idx = (u64*)(p + L.hub_idx);
+  w.hub_base = (u64*)(p + L.hub_base);
   w.plan_gi = (u64*)(p + L.plan_gi);
   w.plan_off = (u64*)(p + L.plan_off);
   w.plan_wfx = (u64*)(p + L.plan_wfx);
@@ -366,16 +376,17 @@ int fora_build_csr(int32_t n, int64_t m, const int32_t* d_rowptr, const int32_t*
   g->cus = device_cu_count();
   if (hipMalloc(&g->info_owned, sizeof(int2) * (size_t)n) != hipSuccess)
     return cleanup(FORA_E_NOMEM, "hipMalloc of the node table failed");
-  if (hipMalloc(&g->flags_owned, 2 * sizeof(int)) != hipSuccess)
+  if (hipMalloc(&g->flags_owned, 3 * sizeof(int)) != hipSuccess)
     return cleanup(FORA_E_NOMEM, "hipMalloc failed");
   if (hipHostMalloc((void**)&g->pinned, sizeof(uint64_t) * 8 * kPinnedSlots, 0) != hipSuccess)
     return cleanup(FORA_E_NOMEM, "hipHostMalloc failed");
   for (int i = kPinnedSlots - 1; i >= 0; --i) g->free_slots.push_back(i);
   g->dev.info = g->info_owned;
-  int host_flags[2] = {0, 0};
+  int host_flags[3] = {0, 0, 0};
   if (hipMemcpyAsync(g->flags_owned, host_flags, sizeof(host_flags), hipMemcpyHostToDevice, s) !=
           hipSuccess ||
-      launch_graph_check(g->dev, g->flags_owned, g->flags_owned + 1, g->info_owned, s) !=
+      launch_graph_check(g->dev, g->flags_owned, g->flags_owned + 1, g->flags_owned + 2,
+                         g->info_owned, s) !=
           hipSuccess ||
       hipMemcpyAsync(host_flags, g->flags_owned, sizeof(host_flags), hipMemcpyDeviceToHost, s) !=
           hipSuccess ||
@@ -387,6 +398,7 @@ int fora_build_csr(int32_t n, int64_t m, const int32_t* d_rowptr, const int32_t*
   if (host_flags[0] & kErrGraphDangling)
     return cleanup(FORA_E_GRAPH, "a node has out-degree 0 (dangling)");
   g->dev.max_deg = host_flags[1];
+  g->dev.n_hubs = host_flags[2];
   *out = g;
   return FORA_OK;
 }
@@ -411,14 +423,14 @@ int fora_graph_info(const fora_graph* g, int32_t* n, int64_t* m, int32_t* max_de
 int fora_workspace_size(const fora_graph* g, int32_t batch, size_t* bytes) {
   if (!g || !bytes) return fail(FORA_E_ARG, "null argument");
   if (batch < 1 || batch > FORA_MAX_BATCH) return fail(FORA_E_ARG, "batch out of range");
-  *bytes = make_layout(g->dev.n, batch).total;
+  *bytes = make_layout(g->dev, batch).total;
   return FORA_OK;
 }
 
 int fora_workspace_views(const fora_graph* g, int32_t batch, void* d_ws, fora_views* v) {
   if (!g || !d_ws || !v) return fail(FORA_E_ARG, "null argument");
   if (batch < 1 || batch > FORA_MAX_BATCH) return fail(FORA_E_ARG, "batch out of range");
-  const Layout L = make_layout(g->dev.n, batch);
+  const Layout L = make_layout(g->dev, batch);
   const Ws w = carve(L, d_ws);
   v->residue = w.r;
   v->reserve = w.q;

@@ -33,8 +33,8 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
 // Problem definition (section 2.1): out-adjacency lists; every node needs an
 // out-neighbour for the walk to move and for Algorithm 1's division by d(v).
 __global__ void k_check_rows(const int32_t* rowptr, int32_t n, int64_t m, int* flags,
-                             int* maxdeg, int2* info) {
-  int local_max = 0;
+                             int* maxdeg, int* hubs, int2* info) {
+  int local_max = 0, local_hubs = 0;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
     const int32_t a = rowptr[v], b = rowptr[v + 1];
@@ -44,9 +44,11 @@ __global__ void k_check_rows(const int32_t* rowptr, int32_t n, int64_t m, int* f
     if (b == a) atomicOr(flags, kErrGraphDangling);
     const int d = b - a;
     local_max = d > local_max ? d : local_max;
+    local_hubs += d > kHubDeg ? 1 : 0;
     info[v] = make_int2(a, d);
   }
   atomicMax(maxdeg, local_max);
+  if (local_hubs) atomicAdd(hubs, local_hubs);
 }
 
 __global__ void k_check_targets(const int32_t* colidx, int64_t m, int32_t n, int* flags) {
@@ -59,10 +61,10 @@ __global__ void k_check_targets(const int32_t* colidx, int64_t m, int32_t n, int
   if (bad) atomicOr(flags, kErrGraphTarget);
 }
 
-hipError_t launch_graph_check(const GraphDev& g, int* d_flags, int* d_maxdeg, int2* info,
-                              hipStream_t s) {
+hipError_t launch_graph_check(const GraphDev& g, int* d_flags, int* d_maxdeg, int* d_hubs,
+                              int2* info, hipStream_t s) {
   const int blocks_n = (int)std::min<int64_t>((g.n + 255) / 256, 16384);
-  k_check_rows<<<blocks_n, 256, 0, s>>>(g.rowptr, g.n, g.m, d_flags, d_maxdeg, info);
+  k_check_rows<<<blocks_n, 256, 0, s>>>(g.rowptr, g.n, g.m, d_flags, d_maxdeg, d_hubs, info);
   if (g.m > 0) {
     const int blocks_m = (int)std::min<int64_t>((g.m + 255) / 256, 16384);
     k_check_targets<<<blocks_m, 256, 0, s>>>(g.colidx, g.m, g.n, d_flags);

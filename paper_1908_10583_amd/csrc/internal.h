@@ -34,6 +34,9 @@ constexpr int kPlanTile = 2048;        // nodes per plan tile (256 threads x 8)
 constexpr int kTopkTile = 4096;        // nodes per top-k block
 constexpr int kHistBins = 2048;        // 11-bit radix digits
 constexpr int kWalkChunk = 512;        // walk ids per work-queue grab
+constexpr int kStatSlots = 64;         // per-query counters are spread over slots
+constexpr int kHubDeg = 2048;          // frontier entries above this are split into pieces
+constexpr int kHubPiece = 2048;        // edges per piece of a split entry
 constexpr double kFx = 4611686018427387904.0;  // 2^62
 
 // Error flags raised by kernels.
@@ -58,7 +61,9 @@ struct QueryDev {
   double omega_unit;
 };
 
-struct QueryStatsDev {
+// Per-query counters, each query's spread over kStatSlots slots so that
+// concurrent blocks add to different addresses; the host sums the slots.
+struct StatSlot {
   u64 pushes;
   u64 edge_ops;
   u64 entries;
@@ -67,7 +72,9 @@ struct QueryStatsDev {
   double r_sum;
   int32_t rounds;
   int32_t term_violations;
+  u64 pad;
 };
+typedef StatSlot QueryStatsDev;
 
 struct Ctrl {
   u64 fr_cnt[2];       // frontier sizes, double-buffered by round parity
@@ -75,6 +82,7 @@ struct Ctrl {
   u64 walks;           // W (all queries)
   u64 chunk_next;      // walk work queue cursor (in chunks)
   u64 log_len;         // frontier log length (push-only path)
+  u64 hub_ctr[2];      // split frontier entries: (count << 40) | pieces, by round parity
   int32_t error;
   int32_t pad;
   u64 round_size[kMaxRoundsLogged];
@@ -87,17 +95,19 @@ struct GraphDev {
   const int32_t* colidx;
   const int2* info;
   int32_t max_deg;
+  int32_t n_hubs;  // nodes with out-degree above kHubDeg
 };
 
 struct Layout {
   size_t ctrl, qstats, queries, r, q, cnt, acc, pi;
-  size_t fr0, fr1, frx;
+  size_t fr0, fr1, frx, hub_idx, hub_base;
   size_t plan_gi, plan_off, plan_wfx;
   size_t tile_cnt, tile_walks, tile_eoff, tile_woff;
   size_t hist, sel, cand_key, cand_id, cand_cnt, blk_ties;
   size_t zero_begin, zero_end;
   size_t total;
-  int64_t cap;  // frontier / plan capacity (batch * n)
+  int64_t cap;      // frontier / plan capacity (batch * n)
+  int64_t hub_cap;  // split-entry capacity per round (batch * n_hubs)
   int64_t tiles_per_row, plan_tiles, topk_blocks;
 };
 
@@ -112,6 +122,8 @@ struct Ws {
   float* pi;
   u64* fr[2];
   float* frx;
+  u64* hub_idx;   // frontier index of each split entry
+  u64* hub_base;  // first piece number of each split entry
   u64* plan_gi;
   u64* plan_off;
   u64* plan_wfx;
@@ -127,7 +139,7 @@ struct Ws {
   uint32_t* blk_ties;  // [batch][topk_blocks]
 };
 
-Layout make_layout(int32_t n, int32_t batch);
+Layout make_layout(const GraphDev& g, int32_t batch);
 Ws carve(const Layout& L, void* base);
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two
@@ -156,11 +168,11 @@ __device__ __forceinline__ uint32_t mul_shift_index(uint32_t hi, uint32_t lo, ui
 
 // ---- launchers (each enqueues on `s`; return hipError_t) -------------------
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
-hipError_t launch_graph_check(const GraphDev& g, int* d_flags, int* d_maxdeg,
+hipError_t launch_graph_check(const GraphDev& g, int* d_flags, int* d_maxdeg, int* d_hubs,
                               int2* info, hipStream_t s);
 hipError_t launch_init_queries(const GraphDev& g, const Ws& w, int batch, hipStream_t s);
-hipError_t launch_push_round(const GraphDev& g, const Ws& w, int batch, int t,
-                             int blocks, bool stats, int32_t* frontier_log,
+hipError_t launch_push_round(const GraphDev& g, const Ws& w, const Layout& L, int batch,
+                             int t, int blocks, bool stats, int32_t* frontier_log,
                              int64_t log_cap, hipStream_t s);
 hipError_t launch_plan(const GraphDev& g, const Ws& w, const Layout& L, int batch,
                        hipStream_t s);

@@ -57,12 +57,13 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_count(
     const size_t tile = (size_t)b * tiles_per_row + blockIdx.x;
     tile_cnt[tile] = (uint32_t)tc;
     tile_walks[tile] = tw;
+    StatSlot* st = &QS[(size_t)b * kStatSlots + (blockIdx.x & (kStatSlots - 1))];
     if (tc) {
-      atomicAdd(&QS[b].entries, tc);
-      atomicAdd(&QS[b].walks, tw);
-      unsafeAtomicAdd(&QS[b].r_sum, trs);
+      atomicAdd(&st->entries, tc);
+      atomicAdd(&st->walks, tw);
+      unsafeAtomicAdd(&st->r_sum, trs);
     }
-    if (tv) atomicAdd(&QS[b].term_violations, (int)tv);
+    if (tv) atomicAdd(&st->term_violations, (int)tv);
   }
 }
 

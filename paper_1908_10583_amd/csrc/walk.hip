@@ -13,7 +13,9 @@
 // a lane whose walk ends takes the next id of the chunk at once (ballot +
 // lane rank), so geometric walk lengths do not leave lanes idle. The entry of
 // a new id is found by a shuffle binary search over a 64-entry window of
-// plan offsets that the wave keeps in registers.
+// plan offsets that the wave keeps in registers. Per-query step totals go to
+// one of kStatSlots slots per query, chosen by wave, so that lanes crossing a
+// query boundary at the same time do not all add to one address.
 #include "internal.h"
 #include "scan.h"
 
@@ -51,6 +53,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
   const u64 E = ctrl->entries;
   const u64 nchunks = (W + kWalkChunk - 1) / kWalkChunk;
   const int lane = threadIdx.x & 63;
+  const int slot = (int)(((blockIdx.x << 2) + (threadIdx.x >> 6)) & (kStatSlots - 1));
 
   bool active = false;
   int b = 0;
@@ -137,7 +140,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
         atomicAdd(&cnt[t], 1u);
         atomicAdd(&acc[t], wfx);
         if (b != stat_b) {
-          if (stat_b >= 0) atomicAdd(&QS[stat_b].steps, stat_steps);
+          if (stat_b >= 0) atomicAdd(&QS[(size_t)stat_b * kStatSlots + slot].steps, stat_steps);
           stat_b = b;
           stat_steps = 0;
         }
@@ -155,8 +158,9 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
   const int b0 = __shfl(stat_b, 0, 64);
   const u64 mine = (stat_b == b0) ? stat_steps : 0ull;
   const u64 sum = wave_sum(mine);
-  if (lane == 0 && b0 >= 0) atomicAdd(&QS[b0].steps, sum);
-  if (stat_b != b0 && stat_b >= 0) atomicAdd(&QS[stat_b].steps, stat_steps);
+  if (lane == 0 && b0 >= 0) atomicAdd(&QS[(size_t)b0 * kStatSlots + slot].steps, sum);
+  if (stat_b != b0 && stat_b >= 0)
+    atomicAdd(&QS[(size_t)stat_b * kStatSlots + slot].steps, stat_steps);
 }
 
 hipError_t launch_walks(const GraphDev& g, const Ws& w, int blocks, hipStream_t s) {
