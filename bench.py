@@ -35,6 +35,24 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def recorded_traffic(kernel: str):
+    """HBM-side bytes per launch from the committed counter record, or None if
+    the kernel's sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", f"{kernel}_*_traffic.json")):
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        try:
+            for src in rec["sources"]:
+                h.update(open(os.path.join(ROOT, src), "rb").read())
+        except OSError:
+            continue
+        if h.hexdigest() == rec["source_sha256"]:
+            return rec["traffic_bytes_per_launch"], os.path.relpath(path, ROOT)
+    return None, None
+
+
 def cpu_baseline(g, src, alpha, eps, k, seed):
     import oracle
     t0 = time.perf_counter()
@@ -54,6 +72,9 @@ def main():
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB device-to-device copy, whose HBM counter "
+                         "readings calibrate FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -74,6 +95,15 @@ def main():
     ids = torch.empty((B, k), dtype=torch.int32, device="cuda:0")
     vals = torch.empty((B, k), dtype=torch.float32, device="cuda:0")
     log(f"workspace {ws.numel()/2**30:.2f} GiB for batch {B}")
+
+    if args.calib_copy:
+        src_t = torch.ones(2**30 // 4, dtype=torch.float32, device="cuda:0")
+        dst_t = torch.empty_like(src_t)
+        torch.cuda.synchronize()
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del src_t, dst_t
 
     for i in range(args.warmup):
         fora.fora_ssppr_batch(G, qs, kmax=k, ws=ws, out=(ids, vals))
@@ -105,9 +135,10 @@ def main():
     walk_s = float(np.mean(walk_ms)) / 1e3
     alg_bytes = BYTES_PER_STEP * per_launch_steps + BYTES_PER_WALK * per_launch_walks
     achieved = alg_bytes / walk_s / 1e9
+    traffic, traffic_src = recorded_traffic("k_walks")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS,
-                    unit="GB/s", frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None,
-                    kernel="k_walks", bytes_per_launch=alg_bytes,
+                    unit="GB/s", frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
+                    traffic_source=traffic_src, kernel="k_walks", bytes_per_launch=alg_bytes,
                     avg_launch_ms=round(walk_s * 1e3, 3))
 
     single = None
