@@ -72,6 +72,7 @@ def main():
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy, whose HBM counter "
                          "readings calibrate FETCH_SIZE / WRITE_SIZE")
@@ -82,7 +83,7 @@ def main():
 
     import torch
     import synth
-    from paper_1908_10583_amd import fora
+    from paper_1908_10583_amd import autotune, fora
 
     alpha, eps, k, seed = 0.2, 0.5, 500, 0
     t0 = time.perf_counter()
@@ -104,6 +105,14 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 1 GiB read + 1 GiB written")
         del src_t, dst_t
+
+    tuning = None
+    if not args.no_autotune:
+        sample = fora.make_queries(srcs[:32], alpha=alpha, eps=eps, k=k, seed=seed, n=g.n)
+        rec = autotune.autotune(G, sample, log=log)
+        tuning = dict(rec["tuning"])
+    graph_rounds = G.get_tuning()["graph_rounds"]
+    G.set_tuning(graph_rounds=0)  # timed region: host-driven rounds, per-phase events
 
     for i in range(args.warmup):
         fora.fora_ssppr_batch(G, qs, kmax=k, ws=ws, out=(ids, vals))
@@ -141,6 +150,21 @@ def main():
                     traffic_source=traffic_src, kernel="k_walks", bytes_per_launch=alg_bytes,
                     avg_launch_ms=round(walk_s * 1e3, 3))
 
+    graph_mode = None
+    if graph_rounds > 0:
+        G.set_tuning(graph_rounds=graph_rounds)
+        fora.fora_ssppr_batch(G, qs, kmax=k, ws=ws, out=(ids, vals))  # capture
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            fora.fora_ssppr_batch(G, qs, kmax=k, ws=ws, out=(ids, vals))
+        torch.cuda.synchronize()
+        dtg = time.perf_counter() - tg
+        graph_mode = dict(queries_per_s=round(B * args.steps / dtg, 2),
+                          walk_steps_per_s=total_steps / dtg, graph_rounds=graph_rounds)
+        log(f"graph replay: {B * args.steps / dtg:.1f} q/s")
+        G.set_tuning(graph_rounds=0)
+
     single = None
     if not args.no_single:
         ws1 = fora.workspace(G, 1)
@@ -176,6 +200,8 @@ def main():
                    "k": k, "batch": B},
         "queries_per_s": round(qps, 2),
         "plain_single_query": single,
+        "graph_replay": graph_mode,
+        "tuning": tuning,
         "phases_ms": {p: round(float(np.mean([stats0[0][p]])), 3)
                       for p in ("ms_push", "ms_plan", "ms_walk", "ms_topk")},
         "per_step": {"walks": per_launch_walks, "walk_steps": per_launch_steps,

@@ -92,6 +92,20 @@ typedef struct fora_views {
   float *pi_hat;              /* q + walk weight, FP32 [batch][n]             */
 } fora_views;
 
+/* Launch shape of the library's kernels for one graph handle. The defaults
+ * suit MI355X; fora_set_tuning replaces them (for example with values an
+ * autotuner measured). Not part of the method: results do not depend on it,
+ * except that graph_rounds > 0 makes fora_ssppr_batch replay a captured HIP
+ * graph (see there). */
+typedef struct fora_tuning {
+  int32_t walk_blocks_per_cu; /* persistent walk grid = CUs x this (1..32)       */
+  int32_t walk_chunk;         /* walk ids per work-queue grab (64..65536, x64)   */
+  int32_t push_blocks_per_cu; /* push grid = CUs x this (1..32)                  */
+  int32_t graph_rounds;       /* 0: host-driven push loop; > 0: capture this
+                                 many push rounds plus plan, walks and top-k in
+                                 one HIP graph per (batch, kmax, buffers)        */
+} fora_tuning;
+
 const char *fora_last_error(void);
 
 /* Graph ingest (section 2.1: a directed graph stored as out-adjacency lists).
@@ -106,6 +120,11 @@ int fora_build_csr(int32_t n, int64_t m, const int32_t *d_rowptr,
 int fora_free_graph(fora_graph *g);
 int fora_graph_info(const fora_graph *g, int32_t *n, int64_t *m,
                     int32_t *max_degree);
+/* Read or replace the launch shape (FORA_E_ARG if a field is out of range).
+ * Replacing it drops the handle's captured graphs. Not thread-safe against
+ * concurrent query calls on the same handle. */
+int fora_get_tuning(const fora_graph *g, fora_tuning *out);
+int fora_set_tuning(fora_graph *g, const fora_tuning *t);
 
 /* Bytes of workspace for `batch` concurrent queries (1..FORA_MAX_BATCH). */
 int fora_workspace_size(const fora_graph *g, int32_t batch, size_t *bytes);
@@ -137,7 +156,13 @@ int fora_ssppr(const fora_graph *g, int32_t src, double alpha, double eps,
  * result is written to d_ids[b*kmax ...], d_vals[b*kmax ...]; kmax must be at
  * least every query's k. Each query's result equals what fora_ssppr returns
  * for it (walk counts bit-identical given identical residues). h_stats
- * (nullable) is an array of `batch` entries. */
+ * (nullable) is an array of `batch` entries.
+ * With tuning.graph_rounds = R > 0 the whole sequence (zero fill, init, R
+ * push rounds, plan, walks, top-k) is captured once per (batch, kmax,
+ * workspace, outputs) into a HIP graph and replayed as one launch; if some
+ * query still has a frontier after R rounds, the plan, walks and top-k of
+ * the replay are skipped and the call finishes them with host-driven rounds.
+ * In graph mode the ms_* fields of the stats are 0. */
 int fora_ssppr_batch(const fora_graph *g, int32_t batch,
                      const fora_query *h_queries, int32_t kmax, void *d_ws,
                      size_t ws_bytes, int32_t *d_ids, float *d_vals,

@@ -4,11 +4,20 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <list>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "internal.h"
+
+// A captured batched pipeline, valid for fixed buffers and shapes.
+struct CapturedGraph {
+  int batch = 0, kmax = 0, rounds = 0;
+  void *ws = nullptr, *ids = nullptr, *vals = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 struct fora_graph {
   fora::GraphDev dev;
@@ -20,6 +29,9 @@ struct fora_graph {
   std::mutex mu;
   uint64_t* pinned = nullptr;
   std::vector<int> free_slots;
+  fora_tuning tuning{8, 512, 4, 0};
+  std::mutex graph_mu;
+  std::list<CapturedGraph> graphs;  // most recently used first
 };
 
 namespace fora {
@@ -108,8 +120,19 @@ int error_code_from_flags(int flags) {
   return FORA_OK;
 }
 
-int walk_blocks(const fora_graph* g) { return g->cus * 8; }
-int push_blocks(const fora_graph* g) { return g->cus * 4; }
+int walk_blocks(const fora_graph* g) { return g->cus * g->tuning.walk_blocks_per_cu; }
+int push_blocks(const fora_graph* g) { return g->cus * g->tuning.push_blocks_per_cu; }
+int walk_chunk(const fora_graph* g) { return g->tuning.walk_chunk; }
+constexpr size_t kMaxCapturedGraphs = 8;
+
+void drop_graphs(fora_graph* g) {
+  std::lock_guard<std::mutex> lk(g->graph_mu);
+  for (auto& c : g->graphs) {
+    if (c.exec) (void)hipGraphExecDestroy(c.exec);
+    if (c.graph) (void)hipGraphDestroy(c.graph);
+  }
+  g->graphs.clear();
+}
 
 struct Call {
   Layout L;
@@ -130,10 +153,10 @@ int prepare(const fora_graph* g, int batch, void* d_ws, size_t ws_bytes, Call& c
 // Push rounds until the frontier is empty; the host checks the frontier size
 // after every group of rounds.
 int run_push(fora_graph* g, const Call& c, int batch, hipStream_t s, bool stats,
-             int32_t* log, int64_t log_cap, int* rounds_out) {
+             int32_t* log, int64_t log_cap, int* rounds_out, int first_round = 0) {
   PinnedSlot ps(g);
   if (!ps.p) return fail(FORA_E_NOMEM, "too many concurrent calls on one graph");
-  int t = 0, group = 4;
+  int t = first_round, group = 4;
   for (;;) {
     for (int i = 0; i < group; ++i, ++t)
       FORA_HIP(launch_push_round(g->dev, c.w, c.L, batch, t, push_blocks(g), stats, log,
@@ -218,6 +241,91 @@ int finish(fora_graph* g, const Call& c, int batch, hipStream_t s, fora_stats* h
   return FORA_OK;
 }
 
+// Everything after the query upload, as one sequence of launches on `s`.
+hipError_t enqueue_pipeline(fora_graph* g, const Call& c, int batch, int rounds, int kmax,
+                            void* d_ws, int32_t* d_ids, float* d_vals, hipStream_t s) {
+  hipError_t e = launch_fill_zero((char*)d_ws + c.L.zero_begin, c.L.zero_end - c.L.zero_begin, s);
+  if (e == hipSuccess) e = launch_init_queries(g->dev, c.w, batch, s);
+  for (int t = 0; t < rounds && e == hipSuccess; ++t)
+    e = launch_push_round(g->dev, c.w, c.L, batch, t, push_blocks(g), true, nullptr, 0, s);
+  if (e == hipSuccess) e = launch_push_gate(c.w, rounds, s);
+  if (e == hipSuccess) e = launch_plan(g->dev, c.w, c.L, batch, s);
+  if (e == hipSuccess) e = launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), s);
+  if (e == hipSuccess) e = launch_topk(g->dev, c.w, c.L, batch, kmax, d_ids, d_vals, s);
+  return e;
+}
+
+// Find or capture the graph for these buffers and shapes.
+int graph_for(fora_graph* g, const Call& c, int batch, int kmax, void* d_ws, int32_t* d_ids,
+              float* d_vals, hipStream_t s, hipGraphExec_t* out) {
+  const int rounds = g->tuning.graph_rounds;
+  std::lock_guard<std::mutex> lk(g->graph_mu);
+  for (auto it = g->graphs.begin(); it != g->graphs.end(); ++it) {
+    if (it->batch == batch && it->kmax == kmax && it->rounds == rounds && it->ws == d_ws &&
+        it->ids == (void*)d_ids && it->vals == (void*)d_vals) {
+      g->graphs.splice(g->graphs.begin(), g->graphs, it);
+      *out = g->graphs.front().exec;
+      return FORA_OK;
+    }
+  }
+  CapturedGraph cg;
+  cg.batch = batch;
+  cg.kmax = kmax;
+  cg.rounds = rounds;
+  cg.ws = d_ws;
+  cg.ids = d_ids;
+  cg.vals = d_vals;
+  hipStream_t cs = nullptr;
+  FORA_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const hipError_t e1 = enqueue_pipeline(g, c, batch, rounds, kmax, d_ws, d_ids, d_vals, cs);
+    e = hipStreamEndCapture(cs, &cg.graph);
+    if (e1 != hipSuccess) e = e1;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&cg.exec, cg.graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  (void)s;
+  if (e != hipSuccess) {
+    if (cg.graph) (void)hipGraphDestroy(cg.graph);
+    return fail(FORA_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e));
+  }
+  g->graphs.push_front(cg);
+  while (g->graphs.size() > kMaxCapturedGraphs) {
+    CapturedGraph& old = g->graphs.back();
+    (void)hipGraphExecDestroy(old.exec);
+    (void)hipGraphDestroy(old.graph);
+    g->graphs.pop_back();
+  }
+  *out = cg.exec;
+  return FORA_OK;
+}
+
+int run_queries_graph(fora_graph* g, const Call& c, int batch, const std::vector<QueryDev>& qd,
+                      int kmax, void* d_ws, int32_t* d_ids, float* d_vals, fora_stats* h_stats,
+                      hipStream_t s) {
+  hipGraphExec_t exec = nullptr;
+  int rc = graph_for(g, c, batch, kmax, d_ws, d_ids, d_vals, s, &exec);
+  if (rc != FORA_OK) return rc;
+  FORA_HIP(hipMemcpyAsync(c.w.queries, qd.data(), sizeof(QueryDev) * batch,
+                          hipMemcpyHostToDevice, s));
+  FORA_HIP(hipGraphLaunch(exec, s));
+  int skip = 0;
+  FORA_HIP(hipMemcpyAsync(&skip, &c.w.ctrl->skip, sizeof(int), hipMemcpyDeviceToHost, s));
+  FORA_HIP(hipStreamSynchronize(s));
+  if (skip) {
+    // some frontier outlived the captured rounds: finish on the host
+    const int zero = 0;
+    FORA_HIP(hipMemcpyAsync(&c.w.ctrl->skip, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+    rc = run_push(g, c, batch, s, true, nullptr, 0, nullptr, g->tuning.graph_rounds);
+    if (rc != FORA_OK) return rc;
+    FORA_HIP(launch_plan(g->dev, c.w, c.L, batch, s));
+    FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), s));
+    FORA_HIP(launch_topk(g->dev, c.w, c.L, batch, kmax, d_ids, d_vals, s));
+  }
+  return finish(g, c, batch, s, h_stats, qd, nullptr);
+}
+
 int run_queries(fora_graph* g, int batch, const fora_query* qs, int kmax, void* d_ws,
                 size_t ws_bytes, int32_t* d_ids, float* d_vals, fora_stats* h_stats,
                 hipStream_t s) {
@@ -234,6 +342,8 @@ int run_queries(fora_graph* g, int batch, const fora_query* qs, int kmax, void* 
     qd[b] = plan_query(g, qs[b]);
   }
   FORA_HIP(hipSetDevice(g->device));
+  if (g->tuning.graph_rounds > 0)
+    return run_queries_graph(g, c, batch, qd, kmax, d_ws, d_ids, d_vals, h_stats, s);
   FORA_HIP(launch_fill_zero((char*)d_ws + c.L.zero_begin, c.L.zero_end - c.L.zero_begin, s));
   FORA_HIP(hipMemcpyAsync(c.w.queries, qd.data(), sizeof(QueryDev) * batch,
                           hipMemcpyHostToDevice, s));
@@ -245,7 +355,7 @@ int run_queries(fora_graph* g, int batch, const fora_query* qs, int kmax, void* 
   pe.mark(1, s);
   FORA_HIP(launch_plan(g->dev, c.w, c.L, batch, s));
   pe.mark(2, s);
-  FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), s));
+  FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), s));
   pe.mark(3, s);
   FORA_HIP(launch_topk(g->dev, c.w, c.L, batch, kmax, d_ids, d_vals, s));
   pe.mark(4, s);
@@ -403,8 +513,30 @@ int fora_build_csr(int32_t n, int64_t m, const int32_t* d_rowptr, const int32_t*
   return FORA_OK;
 }
 
+int fora_get_tuning(const fora_graph* g, fora_tuning* out) {
+  if (!g || !out) return fail(FORA_E_ARG, "null argument");
+  *out = g->tuning;
+  return FORA_OK;
+}
+
+int fora_set_tuning(fora_graph* g, const fora_tuning* t) {
+  if (!g || !t) return fail(FORA_E_ARG, "null argument");
+  if (t->walk_blocks_per_cu < 1 || t->walk_blocks_per_cu > 32)
+    return fail(FORA_E_ARG, "walk_blocks_per_cu must be in [1, 32]");
+  if (t->push_blocks_per_cu < 1 || t->push_blocks_per_cu > 32)
+    return fail(FORA_E_ARG, "push_blocks_per_cu must be in [1, 32]");
+  if (t->walk_chunk < 64 || t->walk_chunk > 65536 || (t->walk_chunk & 63) != 0)
+    return fail(FORA_E_ARG, "walk_chunk must be a multiple of 64 in [64, 65536]");
+  if (t->graph_rounds < 0 || t->graph_rounds > kMaxRoundsLogged)
+    return fail(FORA_E_ARG, "graph_rounds must be in [0, 4096]");
+  drop_graphs(g);
+  g->tuning = *t;
+  return FORA_OK;
+}
+
 int fora_free_graph(fora_graph* g) {
   if (!g) return FORA_OK;
+  drop_graphs(g);
   if (g->info_owned) (void)hipFree(g->info_owned);
   if (g->flags_owned) (void)hipFree(g->flags_owned);
   if (g->pinned) (void)hipHostFree(g->pinned);
@@ -533,7 +665,7 @@ int fora_walk_only(const fora_graph* gc, int64_t entries, const int32_t* d_v,
   FORA_HIP(hipMemcpyAsync(c.w.queries, &qd, sizeof(qd), hipMemcpyHostToDevice, s));
   if (entries > 0) {
     FORA_HIP(launch_walk_plan_from_host(g->dev, c.w, entries, d_v, d_omega, d_w, s));
-    FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), s));
+    FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), s));
   }
   std::vector<QueryDev> qv(1, qd);
   fora_stats st{};

@@ -84,7 +84,7 @@ struct Ctrl {
   u64 log_len;         // frontier log length (push-only path)
   u64 hub_ctr[2];      // split frontier entries: (count << 40) | pieces, by round parity
   int32_t error;
-  int32_t pad;
+  int32_t skip;        // set by the graph's gate when the push needs more rounds
   u64 round_size[kMaxRoundsLogged];
 };
 
@@ -176,7 +176,8 @@ hipError_t launch_push_round(const GraphDev& g, const Ws& w, const Layout& L, in
                              int64_t log_cap, hipStream_t s);
 hipError_t launch_plan(const GraphDev& g, const Ws& w, const Layout& L, int batch,
                        hipStream_t s);
-hipError_t launch_walks(const GraphDev& g, const Ws& w, int blocks, hipStream_t s);
+hipError_t launch_walks(const GraphDev& g, const Ws& w, int blocks, int chunk, hipStream_t s);
+hipError_t launch_push_gate(const Ws& w, int rounds, hipStream_t s);
 hipError_t launch_walk_plan_from_host(const GraphDev& g, const Ws& w, int64_t entries,
                                       const int32_t* d_v, const uint64_t* d_omega,
                                       const double* d_w, hipStream_t s);

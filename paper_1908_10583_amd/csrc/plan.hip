@@ -22,6 +22,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_count(
   __shared__ float s_r[kPlanTile];
   __shared__ u64 s_tmp[kPlanThreads / 64];
   __shared__ double s_tmpd[kPlanThreads / 64];
+  if (ctrl->skip) return;  // uniform: the push has not finished (graph replay)
   const int b = blockIdx.y;
   const int v0 = blockIdx.x * kPlanTile;
   const float* row = r + (size_t)b * n;
@@ -72,6 +73,13 @@ __global__ __launch_bounds__(kScanThreads) void k_plan_scan(
     const uint32_t* tile_cnt, const u64* tile_walks, int64_t ntiles, u64* tile_eoff,
     u64* tile_woff, u64* plan_off, Ctrl* ctrl) {
   __shared__ u64 s_tmp[kScanThreads / 64];
+  if (ctrl->skip) {
+    if (threadIdx.x == 0) {
+      ctrl->entries = 0;
+      ctrl->walks = 0;
+    }
+    return;
+  }
   u64 carry_e = 0, carry_w = 0;
   for (int64_t base = 0; base < ntiles; base += kScanThreads) {
     const int64_t i = base + threadIdx.x;
@@ -99,9 +107,11 @@ __global__ __launch_bounds__(kScanThreads) void k_plan_scan(
 // Tile pass 2: write the plan entries in (query, node) order.
 __global__ __launch_bounds__(kPlanThreads) void k_plan_write(
     const float* __restrict__ r, const QueryDev* __restrict__ Q, int n, int tiles_per_row,
-    const u64* tile_eoff, const u64* tile_woff, u64* plan_gi, u64* plan_off, u64* plan_wfx) {
+    const u64* tile_eoff, const u64* tile_woff, u64* plan_gi, u64* plan_off, u64* plan_wfx,
+    const Ctrl* ctrl) {
   __shared__ float s_r[kPlanTile];
   __shared__ u64 s_tmp[kPlanThreads / 64];
+  if (ctrl->skip) return;
   const int b = blockIdx.y;
   const int v0 = blockIdx.x * kPlanTile;
   const float* row = r + (size_t)b * n;
@@ -148,7 +158,18 @@ hipError_t launch_plan(const GraphDev& g, const Ws& w, const Layout& L, int batc
                                          w.tile_eoff, w.tile_woff, w.plan_off, w.ctrl);
   k_plan_write<<<grid, kPlanThreads, 0, s>>>(w.r, w.queries, g.n, (int)L.tiles_per_row,
                                              w.tile_eoff, w.tile_woff, w.plan_gi, w.plan_off,
-                                             w.plan_wfx);
+                                             w.plan_wfx, w.ctrl);
+  return hipGetLastError();
+}
+
+// Graph replays run a fixed number of push rounds; if any frontier is still
+// non-empty the rest of the replay is skipped and the host finishes it.
+__global__ void k_push_gate(Ctrl* ctrl, int rounds) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctrl->skip = ctrl->fr_cnt[rounds & 1] != 0 ? 1 : 0;
+}
+
+hipError_t launch_push_gate(const Ws& w, int rounds, hipStream_t s) {
+  k_push_gate<<<1, 64, 0, s>>>(w.ctrl, rounds);
   return hipGetLastError();
 }
 

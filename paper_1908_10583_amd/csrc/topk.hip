@@ -24,8 +24,9 @@ __device__ __forceinline__ bool prefix_ok(uint32_t key, int pass, uint32_t prefi
 
 __global__ __launch_bounds__(kTopkThreads) void k_topk_hist(
     int pass, const float* __restrict__ q, const u64* __restrict__ acc, float* __restrict__ pi,
-    int n, uint32_t* hist, const uint32_t* sel) {
+    int n, uint32_t* hist, const uint32_t* sel, const Ctrl* ctrl) {
   __shared__ uint32_t s_hist[kHistBins];
+  if (ctrl->skip) return;
   const int b = blockIdx.y;
   for (int i = threadIdx.x; i < kHistBins; i += kTopkThreads) s_hist[i] = 0;
   __syncthreads();
@@ -57,10 +58,14 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk_hist(
 // sel[b] = {prefix, k still needed, keys above the prefix group, -}.
 __global__ __launch_bounds__(kTopkThreads) void k_topk_select(int pass, uint32_t* hist,
                                                               uint32_t* sel,
-                                                              const QueryDev* Q) {
+                                                              const QueryDev* Q,
+                                                              uint32_t* cand_cnt,
+                                                              const Ctrl* ctrl) {
   __shared__ uint32_t s_tmp[kTopkThreads / 64];
   __shared__ uint32_t s_found[2];
+  if (ctrl->skip) return;
   const int b = blockIdx.x;
+  if (pass == 0 && threadIdx.x == 0) cand_cnt[b] = 0;  // the collect pass appends from 0
   uint32_t* h = hist + (size_t)b * kHistBins;
   const int nb = pass == 2 ? 1024 : kHistBins;
   const int per = nb / kTopkThreads;  // 8 or 4 bins per thread
@@ -110,6 +115,7 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk_collect(
     int32_t* cand_id, uint32_t* cand_cnt, uint32_t* blk_ties, int topk_blocks,
     Ctrl* ctrl) {
   __shared__ uint32_t s_tmp[kTopkThreads / 64];
+  if (ctrl->skip) return;
   const int b = blockIdx.y;
   const uint32_t K = sel[b * 4 + 0];
   const uint32_t above = sel[b * 4 + 2];
@@ -137,8 +143,10 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk_collect(
 }
 
 // One block per query: exclusive scan of the per-block tie counts.
-__global__ __launch_bounds__(1024) void k_topk_tie_scan(uint32_t* blk_ties, int topk_blocks) {
+__global__ __launch_bounds__(1024) void k_topk_tie_scan(uint32_t* blk_ties, int topk_blocks,
+                                                        const Ctrl* ctrl) {
   __shared__ uint32_t s_tmp[16];
+  if (ctrl->skip) return;
   uint32_t* t = blk_ties + (size_t)blockIdx.x * topk_blocks;
   uint32_t carry = 0;
   for (int base = 0; base < topk_blocks; base += 1024) {
@@ -155,8 +163,9 @@ __global__ __launch_bounds__(1024) void k_topk_tie_scan(uint32_t* blk_ties, int 
 // ties in id order (each thread owns 16 consecutive ids).
 __global__ __launch_bounds__(kTopkThreads) void k_topk_ties(
     const float* __restrict__ pi, int n, const uint32_t* sel, const uint32_t* blk_ties,
-    int topk_blocks, uint32_t* cand_key, int32_t* cand_id) {
+    int topk_blocks, uint32_t* cand_key, int32_t* cand_id, const Ctrl* ctrl) {
   __shared__ uint32_t s_tmp[kTopkThreads / 64];
+  if (ctrl->skip) return;
   const int b = blockIdx.y;
   const uint32_t K = sel[b * 4 + 0];
   const uint32_t need = sel[b * 4 + 1];
@@ -190,8 +199,10 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk_ties(
 __global__ __launch_bounds__(1024) void k_topk_sort(const uint32_t* cand_key,
                                                     const int32_t* cand_id,
                                                     const QueryDev* Q, int kmax,
-                                                    int32_t* out_ids, float* out_vals) {
+                                                    int32_t* out_ids, float* out_vals,
+                                                    const Ctrl* ctrl) {
   __shared__ u64 s[FORA_MAX_K];
+  if (ctrl->skip) return;
   const int b = blockIdx.x;
   const int k = Q[b].k;
   int P = 1;
@@ -238,16 +249,19 @@ hipError_t launch_topk(const GraphDev& g, const Ws& w, const Layout& L, int batc
                        int32_t* d_ids, float* d_vals, hipStream_t s) {
   dim3 grid((unsigned)L.topk_blocks, (unsigned)batch);
   for (int pass = 0; pass < 3; ++pass) {
-    k_topk_hist<<<grid, kTopkThreads, 0, s>>>(pass, w.q, w.acc, w.pi, g.n, w.hist, w.sel);
-    k_topk_select<<<batch, kTopkThreads, 0, s>>>(pass, w.hist, w.sel, w.queries);
+    k_topk_hist<<<grid, kTopkThreads, 0, s>>>(pass, w.q, w.acc, w.pi, g.n, w.hist, w.sel,
+                                              w.ctrl);
+    k_topk_select<<<batch, kTopkThreads, 0, s>>>(pass, w.hist, w.sel, w.queries, w.cand_cnt,
+                                                 w.ctrl);
   }
   k_topk_collect<<<grid, kTopkThreads, 0, s>>>(w.pi, g.n, w.sel, w.cand_key, w.cand_id,
                                                w.cand_cnt, w.blk_ties, (int)L.topk_blocks,
                                                w.ctrl);
-  k_topk_tie_scan<<<batch, 1024, 0, s>>>(w.blk_ties, (int)L.topk_blocks);
+  k_topk_tie_scan<<<batch, 1024, 0, s>>>(w.blk_ties, (int)L.topk_blocks, w.ctrl);
   k_topk_ties<<<grid, kTopkThreads, 0, s>>>(w.pi, g.n, w.sel, w.blk_ties, (int)L.topk_blocks,
-                                            w.cand_key, w.cand_id);
-  k_topk_sort<<<batch, 1024, 0, s>>>(w.cand_key, w.cand_id, w.queries, kmax, d_ids, d_vals);
+                                            w.cand_key, w.cand_id, w.ctrl);
+  k_topk_sort<<<batch, 1024, 0, s>>>(w.cand_key, w.cand_id, w.queries, kmax, d_ids, d_vals,
+                                     w.ctrl);
   return hipGetLastError();
 }
 

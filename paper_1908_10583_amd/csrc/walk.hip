@@ -8,7 +8,7 @@
 // floor(U * d(x) / 2^64) of x, where U = word1 * 2^32 + word2. At its end
 // point t it adds 1 to cnt[t] and its entry's fixed-point weight to acc[t].
 //
-// Schedule: a persistent grid; each wavefront takes chunks of kWalkChunk
+// Schedule: a persistent grid; each wavefront takes chunks of `chunk`
 // consecutive walk ids from a device work queue and keeps all 64 lanes busy:
 // a lane whose walk ends takes the next id of the chunk at once (ballot +
 // lane rank), so geometric walk lengths do not leave lanes idle. The entry of
@@ -47,11 +47,11 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
     const u64* __restrict__ plan_gi, const u64* __restrict__ plan_off,
     const u64* __restrict__ plan_wfx, Ctrl* ctrl, const QueryDev* __restrict__ Q,
     QueryStatsDev* QS, const int2* __restrict__ info, const int32_t* __restrict__ colidx,
-    int n, uint32_t* __restrict__ cnt, u64* __restrict__ acc) {
-  if (ctrl->error) return;
+    int n, uint32_t* __restrict__ cnt, u64* __restrict__ acc, int chunk) {
+  if (ctrl->error || ctrl->skip) return;
   const u64 W = ctrl->walks;
   const u64 E = ctrl->entries;
-  const u64 nchunks = (W + kWalkChunk - 1) / kWalkChunk;
+  const u64 nchunks = (W + chunk - 1) / (u64)chunk;
   const int lane = threadIdx.x & 63;
   const int slot = (int)(((blockIdx.x << 2) + (threadIdx.x >> 6)) & (kStatSlots - 1));
 
@@ -77,8 +77,8 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
         if (c >= nchunks) {
           more = false;
         } else {
-          cursor = c * (u64)kWalkChunk;
-          cend = cursor + kWalkChunk < W ? cursor + kWalkChunk : W;
+          cursor = c * (u64)chunk;
+          cend = cursor + chunk < W ? cursor + chunk : W;
           ebase = wave_find_entry(plan_off, E, cursor);
           woff = (ebase + lane <= E) ? plan_off[ebase + lane] : ~0ull;
         }
@@ -163,9 +163,9 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
     atomicAdd(&QS[(size_t)stat_b * kStatSlots + slot].steps, stat_steps);
 }
 
-hipError_t launch_walks(const GraphDev& g, const Ws& w, int blocks, hipStream_t s) {
+hipError_t launch_walks(const GraphDev& g, const Ws& w, int blocks, int chunk, hipStream_t s) {
   k_walks<<<blocks, kWalkBlock, 0, s>>>(w.plan_gi, w.plan_off, w.plan_wfx, w.ctrl, w.queries,
-                                        w.qstats, g.info, g.colidx, g.n, w.cnt, w.acc);
+                                        w.qstats, g.info, g.colidx, g.n, w.cnt, w.acc, chunk);
   return hipGetLastError();
 }
 

@@ -48,6 +48,14 @@ class fora_query(ctypes.Structure):
                 ("rmax", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
+class fora_tuning(ctypes.Structure):
+    _fields_ = [("walk_blocks_per_cu", ctypes.c_int32), ("walk_chunk", ctypes.c_int32),
+                ("push_blocks_per_cu", ctypes.c_int32), ("graph_rounds", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class fora_views(ctypes.Structure):
     _fields_ = [("residue", ctypes.c_void_p), ("reserve", ctypes.c_void_p),
                 ("walk_count", ctypes.c_void_p), ("walk_weight_fx", ctypes.c_void_p),
@@ -68,6 +76,8 @@ def _load():
         "fora_free_graph": ([P], ctypes.c_int),
         "fora_graph_info": ([P, ctypes.POINTER(I32), ctypes.POINTER(I64), ctypes.POINTER(I32)],
                             ctypes.c_int),
+        "fora_get_tuning": ([P, ctypes.POINTER(fora_tuning)], ctypes.c_int),
+        "fora_set_tuning": ([P, ctypes.POINTER(fora_tuning)], ctypes.c_int),
         "fora_workspace_size": ([P, I32, ctypes.POINTER(SZ)], ctypes.c_int),
         "fora_workspace_views": ([P, I32, P, ctypes.POINTER(fora_views)], ctypes.c_int),
         "fora_ssppr": ([P, I32, F64, F64, F64, F64, I32, F64, U64, P, SZ, P, P,
@@ -90,6 +100,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = ["fora_last_error", "fora_build_csr", "fora_free_graph", "fora_graph_info",
+            "fora_get_tuning", "fora_set_tuning",
             "fora_workspace_size", "fora_workspace_views", "fora_ssppr", "fora_ssppr_batch",
             "fora_push_only", "fora_walk_only", "fora_philox"]
 
@@ -137,6 +148,18 @@ class Graph:
     def from_numpy(cls, rowptr: np.ndarray, colidx: np.ndarray, device="cuda"):
         return cls(torch.from_numpy(np.ascontiguousarray(rowptr, np.int32)).to(device),
                    torch.from_numpy(np.ascontiguousarray(colidx, np.int32)).to(device))
+
+    def get_tuning(self) -> dict:
+        t = fora_tuning()
+        _check(_lib.fora_get_tuning(self.handle, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = fora_tuning()
+        _check(_lib.fora_get_tuning(self.handle, ctypes.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        _check(_lib.fora_set_tuning(self.handle, ctypes.byref(t)))
 
     def close(self):
         if getattr(self, "handle", None) is not None:

@@ -1,0 +1,170 @@
+"""Batched queries, captured-graph replays and the autotuner (GPU).
+
+Batched and graph-replayed results are compared with single-query eager calls
+and with the oracle. FP32 residues may differ in the last bits between runs
+(atomic order), so residues and reserves are compared to 1e-5 and walk counts
+bit-exactly wherever the walk plans (functions of the residues) agree.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1908_10583_amd import autotune, fora  # noqa: E402
+
+RTOL, ATOL = 1e-5, 1e-12
+
+
+def close(g, o, rtol=RTOL, atol=ATOL):
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    return np.abs(g - o) <= rtol * np.abs(o) + atol
+
+
+@pytest.fixture(scope="module")
+def g1k():
+    return synth.uniform_out_graph(1000, 10, seed=1)
+
+
+@pytest.fixture
+def G1k(g1k):
+    G = fora.Graph.from_numpy(g1k.rowptr, g1k.colidx)
+    yield G
+    G.close()
+
+
+def _rows(G, B, ws):
+    v = fora.fora_workspace_views(G, B, ws)
+    return {k: t.cpu().numpy().copy() for k, t in v.items()}
+
+
+def _same_query(a, b, i, j, omega_unit):
+    """Row i of result a against row j of result b."""
+    assert np.all(close(a["reserve"][i], b["reserve"][j]))
+    assert np.all(close(a["residue"][i], b["residue"][j]))
+    om_a = np.ceil(a["residue"][i].astype(np.float64) * omega_unit)
+    om_b = np.ceil(b["residue"][j].astype(np.float64) * omega_unit)
+    if np.array_equal(om_a, om_b):
+        assert np.array_equal(a["walk_count"][i], b["walk_count"][j])
+    assert np.all(close(a["pi_hat"][i], b["pi_hat"][j], rtol=2e-5, atol=1e-9))
+
+
+def test_tuning_validation(G1k):
+    t = G1k.get_tuning()
+    assert t["walk_chunk"] % 64 == 0 and t["graph_rounds"] == 0
+    for bad in (dict(walk_chunk=100), dict(walk_chunk=0), dict(walk_blocks_per_cu=0),
+                dict(push_blocks_per_cu=99), dict(graph_rounds=-1)):
+        with pytest.raises(fora.FORAError) as ei:
+            G1k.set_tuning(**bad)
+        assert ei.value.code == fora.FORA_E_ARG
+    assert G1k.get_tuning() == t
+
+
+@pytest.mark.parametrize("shape", [dict(walk_blocks_per_cu=1, walk_chunk=64, push_blocks_per_cu=1),
+                                   dict(walk_blocks_per_cu=16, walk_chunk=4096,
+                                        push_blocks_per_cu=16)])
+def test_results_do_not_depend_on_tuning(g1k, G1k, shape):
+    ref = oracle.fora(g1k, 7, k=50, seed=3)
+    G1k.set_tuning(**shape)
+    ws = fora.workspace(G1k, 1)
+    res = fora.fora_ssppr(G1k, 7, k=50, seed=3, ws=ws, stats=True)
+    v = _rows(G1k, 1, ws)
+    assert res.stats["rounds"] == ref["rounds"]
+    assert np.all(close(v["reserve"][0], ref["q"]))
+    om = np.ceil(v["residue"][0].astype(np.float64) * res.stats["omega_unit"])
+    om_ref = np.zeros(g1k.n)
+    om_ref[ref["plan"][0]] = ref["plan"][1]
+    if np.array_equal(om, om_ref):
+        assert np.array_equal(v["walk_count"][0].view(np.uint32).astype(np.uint64), ref["cnt"])
+        assert res.stats["steps"] == ref["steps"]
+
+
+def test_graph_replays_match_eager(g1k, G1k):
+    srcs = [0, 3, 3, 500, 999, 42]
+    qs = fora.make_queries(srcs, k=50, seed=[1, 2, 2, 3, 4, 5], n=g1k.n)
+    B = len(srcs)
+    ws_e = fora.workspace(G1k, B)
+    eager = fora.fora_ssppr_batch(G1k, qs, ws=ws_e, stats=True)
+    ref = _rows(G1k, B, ws_e)
+    ref_ids = eager.ids.cpu().numpy()
+    omega_unit = eager.stats[0]["omega_unit"]
+    rounds = max(s["rounds"] for s in eager.stats)
+    G1k.set_tuning(graph_rounds=rounds + 2)
+    ws_g = fora.workspace(G1k, B)
+    out = (torch.empty((B, 50), dtype=torch.int32, device="cuda"),
+           torch.empty((B, 50), dtype=torch.float32, device="cuda"))
+    for rep in range(3):
+        res = fora.fora_ssppr_batch(G1k, qs, ws=ws_g, out=out, stats=True)
+        torch.cuda.synchronize()
+        got = _rows(G1k, B, ws_g)
+        for b in range(B):
+            _same_query(got, ref, b, b, omega_unit)
+            order = np.lexsort((np.arange(g1k.n), -got["pi_hat"][b]))[:50]
+            assert np.array_equal(res.ids[b].cpu().numpy(), order)
+        assert [s["rounds"] for s in res.stats] == [s["rounds"] for s in eager.stats]
+        # eager work on the same stream between replays
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+        fora.fora_ssppr(G1k, 11, k=5, seed=9)
+    assert ref_ids.shape == (B, 50)
+
+
+def test_graph_with_too_few_rounds_finishes_on_host(g1k, G1k):
+    srcs = [0, 17]
+    qs = fora.make_queries(srcs, k=50, seed=1, n=g1k.n)
+    ws_e = fora.workspace(G1k, 2)
+    eager = fora.fora_ssppr_batch(G1k, qs, ws=ws_e, stats=True)
+    ref = _rows(G1k, 2, ws_e)
+    G1k.set_tuning(graph_rounds=2)  # far fewer than the push needs
+    ws_g = fora.workspace(G1k, 2)
+    for _ in range(2):
+        res = fora.fora_ssppr_batch(G1k, qs, ws=ws_g, stats=True)
+        got = _rows(G1k, 2, ws_g)
+        for b in range(2):
+            _same_query(got, ref, b, b, eager.stats[0]["omega_unit"])
+        assert [s["rounds"] for s in res.stats] == [s["rounds"] for s in eager.stats]
+
+
+def test_mixed_parameters_match_single_calls(g1k, G1k):
+    srcs = [5, 5, 900, 64]
+    eps = [0.5, 0.3, 0.5, 0.2]
+    ks = [10, 50, 1, 200]
+    alphas = [0.2, 0.2, 0.15, 0.3]
+    qs = fora.make_queries(srcs, alpha=alphas, eps=eps, k=ks, seed=[0, 1, 2, 3], n=g1k.n)
+    B = len(srcs)
+    ws = fora.workspace(G1k, B)
+    bat = fora.fora_ssppr_batch(G1k, qs, kmax=200, ws=ws, stats=True)
+    got = _rows(G1k, B, ws)
+    ws1 = fora.workspace(G1k, 1)
+    for b in range(B):
+        single = fora.fora_ssppr(G1k, srcs[b], alphas[b], eps[b], k=ks[b], seed=b, ws=ws1,
+                                 stats=True)
+        one = _rows(G1k, 1, ws1)
+        _same_query(got, one, b, 0, single.stats["omega_unit"])
+        assert bat.stats[b]["omega_unit"] == single.stats["omega_unit"]
+        assert bat.stats[b]["rmax"] == single.stats["rmax"]
+        ids = bat.ids[b].cpu().numpy()
+        assert np.all(ids[ks[b]:] == -1)
+        ref = oracle.fora(g1k, srcs[b], alpha=alphas[b], eps=eps[b], k=ks[b], seed=b)
+        assert bat.stats[b]["rounds"] == ref["rounds"]
+
+
+def test_autotune_sets_and_caches(g1k, G1k, tmp_path):
+    qs = fora.make_queries([0, 1, 2, 3], k=50, n=g1k.n)
+    path = str(tmp_path / "tune.json")
+    rec = autotune.autotune(G1k, qs, path=path)
+    assert not rec["cached"]
+    t = G1k.get_tuning()
+    assert t == rec["tuning"]
+    rec2 = autotune.autotune(G1k, qs, path=path)
+    assert rec2["cached"] and rec2["tuning"] == t
+    res = fora.fora_ssppr_batch(G1k, qs, stats=True)
+    ref = oracle.fora(g1k, 2, k=50, seed=0)
+    assert res.stats[2]["rounds"] == ref["rounds"]
