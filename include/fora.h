@@ -63,7 +63,7 @@ typedef struct fora_stats {
   float ms_plan;           /* (for a batch: the whole batch's phase, repeated  */
   float ms_walk;           /*  in every entry); ms_walk spans exactly the walk */
   float ms_topk;           /*  kernel launch                                   */
-  uint32_t reserved;
+  uint32_t pull_rounds;    /* push rounds that ran as a pull over in-edges     */
 } fora_stats;
 
 /* One query of a batch. */
@@ -104,6 +104,9 @@ typedef struct fora_tuning {
   int32_t graph_rounds;       /* 0: host-driven push loop; > 0: capture this
                                  many push rounds plus plan, walks and top-k in
                                  one HIP graph per (batch, kmax, buffers)        */
+  int32_t pull_ratio;         /* a query's push round runs as a pull over the
+                                 reverse graph when its frontier edges times
+                                 this exceed n + m (0: never pull)               */
 } fora_tuning;
 
 const char *fora_last_error(void);

@@ -2,7 +2,7 @@
 
 It times real batched calls on the caller's graph and queries with the
 library's own per-phase HIP-event timers, picks the fastest shape phase by
-phase (push grid, then walk grid x walk chunk), decides whether replaying a
+phase (pull/push switch point, push grid, then walk grid x walk chunk), decides whether replaying a
 captured HIP graph beats the host-driven push loop, and caches the result in
 a JSON file keyed by device, graph size and batch size. Results never depend
 on the tuning; only speed does.
@@ -17,6 +17,7 @@ import torch
 
 from . import fora
 
+PULL_RATIOS = (0, 4, 16, 64)
 PUSH_BLOCKS = (2, 4, 8, 16)
 WALK_BLOCKS = (4, 8, 12, 16)
 WALK_CHUNKS = (256, 512, 1024, 2048)
@@ -74,10 +75,19 @@ def autotune(G: fora.Graph, queries, path: str | None = None, force: bool = Fals
     ws = fora.workspace(G, B)
     out = (torch.empty((B, kmax), dtype=torch.int32, device=G.device),
            torch.empty((B, kmax), dtype=torch.float32, device=G.device))
-    base = dict(walk_blocks_per_cu=8, walk_chunk=512, push_blocks_per_cu=4, graph_rounds=0)
+    base = dict(walk_blocks_per_cu=8, walk_chunk=512, push_blocks_per_cu=4, graph_rounds=0,
+                pull_ratio=16)
     G.set_tuning(**base)
     _timed(G, queries, ws, out, reps=1)  # warm-up
     trials = []
+    best_ratio = None
+    for pr in PULL_RATIOS:
+        G.set_tuning(**dict(base, pull_ratio=pr))
+        m = _timed(G, queries, ws, out)
+        trials.append(dict(pull_ratio=pr, **m))
+        if best_ratio is None or m["push"] < best_ratio[1]:
+            best_ratio = (pr, m["push"])
+    base["pull_ratio"] = best_ratio[0]
     best_push = None
     for pb in PUSH_BLOCKS:
         G.set_tuning(**dict(base, push_blocks_per_cu=pb))

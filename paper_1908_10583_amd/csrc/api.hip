@@ -23,13 +23,17 @@ struct fora_graph {
   fora::GraphDev dev;
   int2* info_owned = nullptr;
   int* flags_owned = nullptr;  // 3 ints: check flags, max degree, hub count
+  int32_t* in_rowptr_owned = nullptr;
+  int32_t* in_colidx_owned = nullptr;
+  int32_t* inhub_node_owned = nullptr;
+  fora::u64* inhub_base_owned = nullptr;
   int device = 0;
   int cus = 256;
   // pinned host slots for the small read-backs of the push loop
   std::mutex mu;
   uint64_t* pinned = nullptr;
   std::vector<int> free_slots;
-  fora_tuning tuning{8, 512, 4, 0};
+  fora_tuning tuning{8, 512, 4, 0, fora::kPullRatio};
   std::mutex graph_mu;
   std::list<CapturedGraph> graphs;  // most recently used first
 };
@@ -159,8 +163,8 @@ int run_push(fora_graph* g, const Call& c, int batch, hipStream_t s, bool stats,
   int t = first_round, group = 4;
   for (;;) {
     for (int i = 0; i < group; ++i, ++t)
-      FORA_HIP(launch_push_round(g->dev, c.w, c.L, batch, t, push_blocks(g), stats, log,
-                                 log_cap, s));
+      FORA_HIP(launch_push_round(g->dev, c.w, c.L, batch, t, push_blocks(g),
+                                 g->tuning.pull_ratio, log, log_cap, s));
     FORA_HIP(hipMemcpyAsync(ps.p, &c.w.ctrl->fr_cnt[t & 1], sizeof(uint64_t),
                             hipMemcpyDeviceToHost, s));
     FORA_HIP(hipStreamSynchronize(s));
@@ -225,6 +229,7 @@ int finish(fora_graph* g, const Call& c, int batch, hipStream_t s, fora_stats* h
         o.walks += q.walks;
         o.steps += q.steps;
         o.r_sum += q.r_sum;
+        o.pull_rounds += (uint32_t)q.pull_rounds;
       }
       o.rmax = qd[b].rmax;
       o.omega_unit = qd[b].omega_unit;
@@ -247,7 +252,8 @@ hipError_t enqueue_pipeline(fora_graph* g, const Call& c, int batch, int rounds,
   hipError_t e = launch_fill_zero((char*)d_ws + c.L.zero_begin, c.L.zero_end - c.L.zero_begin, s);
   if (e == hipSuccess) e = launch_init_queries(g->dev, c.w, batch, s);
   for (int t = 0; t < rounds && e == hipSuccess; ++t)
-    e = launch_push_round(g->dev, c.w, c.L, batch, t, push_blocks(g), true, nullptr, 0, s);
+    e = launch_push_round(g->dev, c.w, c.L, batch, t, push_blocks(g), g->tuning.pull_ratio,
+                          nullptr, 0, s);
   if (e == hipSuccess) e = launch_push_gate(c.w, rounds, s);
   if (e == hipSuccess) e = launch_plan(g->dev, c.w, c.L, batch, s);
   if (e == hipSuccess) e = launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), s);
@@ -390,7 +396,11 @@ Layout make_layout(const GraphDev& g, int32_t batch) {
   L.acc = take(8 * cap);
   L.hist = take(4 * (size_t)kHistBins * batch);
   L.cand_cnt = take(4 * (size_t)batch);
+  L.incd = take(4 * cap);
+  L.ecnt = take(8 * 2 * (size_t)kStatSlots * batch);
   L.zero_end = align_up(off, 256);
+  L.mode = take(4 * (size_t)batch);
+  L.pull_list = take(4 * (size_t)batch);
   // written before being read
   L.queries = take(sizeof(QueryDev) * batch);
   L.pi = take(4 * cap);
@@ -430,6 +440,10 @@ Ws carve(const Layout& L, void* base) {
   w.frx = (float*)(p + L.frx);
   w.hub_idx = (u64*)(p + L.hub_idx);
   w.hub_base = (u64*)(p + L.hub_base);
+  w.incd = (float*)(p + L.incd);
+  w.ecnt = (u64*)(p + L.ecnt);
+  w.mode = (int32_t*)(p + L.mode);
+  w.pull_list = (int32_t*)(p + L.pull_list);
   w.plan_gi = (u64*)(p + L.plan_gi);
   w.plan_off = (u64*)(p + L.plan_off);
   w.plan_wfx = (u64*)(p + L.plan_wfx);
@@ -458,6 +472,81 @@ int device_cu_count() {
 
 using namespace fora;
 
+namespace {
+
+// Reverse (in-edge) CSR and the list of nodes whose in-degree needs pieces,
+// for pull-mode push rounds. Allocated once per graph handle.
+int build_reverse(fora_graph* g, hipStream_t s) {
+  const int32_t n = g->dev.n;
+  const int64_t m = g->dev.m;
+  int32_t* cursor = nullptr;
+  uint32_t* tsum = nullptr;
+  int32_t* list = nullptr;
+  const int64_t tiles = (n + 2047) / 2048;
+  const int32_t list_cap = (int32_t)std::min<int64_t>(n, m / (kHubDeg + 1) + 1);
+  auto release = [&]() {
+    if (cursor) (void)hipFree(cursor);
+    if (tsum) (void)hipFree(tsum);
+    if (list) (void)hipFree(list);
+  };
+  if (hipMalloc(&g->in_rowptr_owned, sizeof(int32_t) * ((size_t)n + 1)) != hipSuccess ||
+      hipMalloc(&g->in_colidx_owned, sizeof(int32_t) * (size_t)std::max<int64_t>(m, 1)) !=
+          hipSuccess ||
+      hipMalloc(&cursor, sizeof(int32_t) * (size_t)n) != hipSuccess ||
+      hipMalloc(&tsum, sizeof(uint32_t) * (size_t)tiles) != hipSuccess ||
+      hipMalloc(&list, sizeof(int32_t) * ((size_t)list_cap + 1)) != hipSuccess) {
+    release();
+    return fail(FORA_E_NOMEM, "hipMalloc of the reverse graph failed");
+  }
+  std::vector<int32_t> in_rowptr((size_t)n + 1);
+  int32_t count = 0;
+  hipError_t e = launch_build_reverse(g->dev, g->in_rowptr_owned, g->in_colidx_owned, cursor,
+                                      tsum, s);
+  if (e == hipSuccess) e = launch_fill_zero(list + list_cap, sizeof(int32_t), s);
+  if (e == hipSuccess)
+    e = launch_list_inhubs(g->in_rowptr_owned, n, list, list + list_cap, list_cap, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&count, list + list_cap, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(in_rowptr.data(), g->in_rowptr_owned, sizeof(int32_t) * in_rowptr.size(),
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  std::vector<int32_t> hubs;
+  if (e == hipSuccess && count > 0) {
+    hubs.resize((size_t)std::min(count, list_cap));
+    e = hipMemcpy(hubs.data(), list, sizeof(int32_t) * hubs.size(), hipMemcpyDeviceToHost);
+  }
+  release();
+  if (e != hipSuccess) return fail(FORA_E_HIP, std::string("reverse graph: ") + hipGetErrorString(e));
+  std::sort(hubs.begin(), hubs.end());
+  std::vector<u64> base(hubs.size());
+  u64 pieces = 0;
+  for (size_t i = 0; i < hubs.size(); ++i) {
+    base[i] = pieces;
+    const int32_t d = in_rowptr[hubs[i] + 1] - in_rowptr[hubs[i]];
+    pieces += (u64)((d + kHubPiece - 1) / kHubPiece);
+  }
+  if (!hubs.empty()) {
+    if (hipMalloc(&g->inhub_node_owned, sizeof(int32_t) * hubs.size()) != hipSuccess ||
+        hipMalloc(&g->inhub_base_owned, sizeof(u64) * hubs.size()) != hipSuccess)
+      return fail(FORA_E_NOMEM, "hipMalloc of the in-hub table failed");
+    if (hipMemcpy(g->inhub_node_owned, hubs.data(), sizeof(int32_t) * hubs.size(),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g->inhub_base_owned, base.data(), sizeof(u64) * base.size(),
+                  hipMemcpyHostToDevice) != hipSuccess)
+      return fail(FORA_E_HIP, "upload of the in-hub table failed");
+  }
+  g->dev.in_rowptr = g->in_rowptr_owned;
+  g->dev.in_colidx = g->in_colidx_owned;
+  g->dev.n_inhubs = (int32_t)hubs.size();
+  g->dev.inhub_node = g->inhub_node_owned;
+  g->dev.inhub_base = g->inhub_base_owned;
+  g->dev.inhub_pieces = pieces;
+  return FORA_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* fora_last_error(void) { return g_err.c_str(); }
@@ -476,6 +565,10 @@ int fora_build_csr(int32_t n, int64_t m, const int32_t* d_rowptr, const int32_t*
   g->dev.rowptr = d_rowptr;
   g->dev.colidx = d_colidx;
   auto cleanup = [&](int code, const std::string& msg) {
+    if (g->in_rowptr_owned) (void)hipFree(g->in_rowptr_owned);
+    if (g->in_colidx_owned) (void)hipFree(g->in_colidx_owned);
+    if (g->inhub_node_owned) (void)hipFree(g->inhub_node_owned);
+    if (g->inhub_base_owned) (void)hipFree(g->inhub_base_owned);
     if (g->info_owned) (void)hipFree(g->info_owned);
     if (g->flags_owned) (void)hipFree(g->flags_owned);
     if (g->pinned) (void)hipHostFree(g->pinned);
@@ -509,6 +602,11 @@ int fora_build_csr(int32_t n, int64_t m, const int32_t* d_rowptr, const int32_t*
     return cleanup(FORA_E_GRAPH, "a node has out-degree 0 (dangling)");
   g->dev.max_deg = host_flags[1];
   g->dev.n_hubs = host_flags[2];
+  const int rrc = build_reverse(g, s);
+  if (rrc != FORA_OK) {
+    const std::string msg = g_err;
+    return cleanup(rrc, msg);
+  }
   *out = g;
   return FORA_OK;
 }
@@ -529,6 +627,7 @@ int fora_set_tuning(fora_graph* g, const fora_tuning* t) {
     return fail(FORA_E_ARG, "walk_chunk must be a multiple of 64 in [64, 65536]");
   if (t->graph_rounds < 0 || t->graph_rounds > kMaxRoundsLogged)
     return fail(FORA_E_ARG, "graph_rounds must be in [0, 4096]");
+  if (t->pull_ratio < 0) return fail(FORA_E_ARG, "pull_ratio must be >= 0");
   drop_graphs(g);
   g->tuning = *t;
   return FORA_OK;
@@ -537,6 +636,10 @@ int fora_set_tuning(fora_graph* g, const fora_tuning* t) {
 int fora_free_graph(fora_graph* g) {
   if (!g) return FORA_OK;
   drop_graphs(g);
+  if (g->in_rowptr_owned) (void)hipFree(g->in_rowptr_owned);
+  if (g->in_colidx_owned) (void)hipFree(g->in_colidx_owned);
+  if (g->inhub_node_owned) (void)hipFree(g->inhub_node_owned);
+  if (g->inhub_base_owned) (void)hipFree(g->inhub_base_owned);
   if (g->info_owned) (void)hipFree(g->info_owned);
   if (g->flags_owned) (void)hipFree(g->flags_owned);
   if (g->pinned) (void)hipHostFree(g->pinned);

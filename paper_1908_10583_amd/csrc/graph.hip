@@ -1,6 +1,7 @@
 // Graph ingest checks, the per-node {row start, out-degree} table, a zero
 // fill, and the device Philox block kernel used for RNG checks.
 #include "internal.h"
+#include "scan.h"
 
 namespace fora {
 
@@ -83,6 +84,112 @@ hipError_t launch_philox(int64_t count, const uint32_t* d_ctr, uint32_t k0, uint
   if (count <= 0) return hipSuccess;
   const int blocks = (int)std::min<int64_t>((count + 255) / 256, 16384);
   k_philox<<<blocks, 256, 0, s>>>(count, (const uint4*)d_ctr, k0, k1, (uint4*)d_out);
+  return hipGetLastError();
+}
+
+}  // namespace fora
+
+namespace fora {
+
+// ---- reverse (in-edge) CSR, built once at ingest for pull-mode push rounds
+constexpr int kScanTile = 2048;
+
+__global__ void k_indeg(const int32_t* __restrict__ colidx, int64_t m, int32_t* indeg) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&indeg[colidx[e]], 1);
+}
+
+__global__ __launch_bounds__(256) void k_tile_sum(const int32_t* __restrict__ x, int64_t n,
+                                                  uint32_t* tsum) {
+  __shared__ uint32_t s_tmp[4];
+  uint32_t acc = 0;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  for (int k = threadIdx.x; k < kScanTile; k += 256)
+    if (base + k < n) acc += (uint32_t)x[base + k];
+  const uint32_t t = block_sum(acc, s_tmp);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(1024) void k_tile_scan(uint32_t* tsum, int64_t ntiles) {
+  __shared__ uint32_t s_tmp[16];
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < ntiles; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const uint32_t c = i < ntiles ? tsum[i] : 0u;
+    uint32_t tot;
+    const uint32_t p = block_exclusive_scan(c, s_tmp, tot);
+    if (i < ntiles) tsum[i] = carry + p;
+    carry += tot;
+  }
+}
+
+// out[i] = sum of x[0..i); each thread scans 8 consecutive values
+__global__ __launch_bounds__(256) void k_tile_apply(const int32_t* __restrict__ x, int64_t n,
+                                                    const uint32_t* tsum, int32_t* out,
+                                                    int32_t* out2) {
+  __shared__ uint32_t s_tmp[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 8;
+  uint32_t v[8], loc = 0;
+  for (int k = 0; k < 8; ++k) {
+    v[k] = base + k < n ? (uint32_t)x[base + k] : 0u;
+    loc += v[k];
+  }
+  uint32_t tot;
+  uint32_t run = tsum[blockIdx.x] + block_exclusive_scan(loc, s_tmp, tot);
+  for (int k = 0; k < 8; ++k) {
+    if (base + k < n) {
+      out[base + k] = (int32_t)run;
+      out2[base + k] = (int32_t)run;
+    }
+    if (base + k == n - 1) out[n] = (int32_t)(run + v[k]);
+    run += v[k];
+  }
+}
+
+__global__ void k_fill_rev(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+                           int32_t n, int32_t* cursor, int32_t* in_colidx) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    for (int32_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+      const int32_t pos = atomicAdd(&cursor[colidx[e]], 1);
+      in_colidx[pos] = (int32_t)v;
+    }
+}
+
+__global__ void k_list_inhubs(const int32_t* __restrict__ in_rowptr, int32_t n, int32_t* list,
+                              int32_t* count, int32_t cap) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    if (in_rowptr[v + 1] - in_rowptr[v] > kHubDeg) {
+      const int32_t pos = atomicAdd(count, 1);
+      if (pos < cap) list[pos] = (int32_t)v;
+    }
+}
+
+// Builds in_rowptr[n+1] and in_colidx[m] (caller-allocated) using the
+// scratch arrays cursor[n] and tsum[ceil(n / 2048)].
+hipError_t launch_build_reverse(const GraphDev& g, int32_t* in_rowptr, int32_t* in_colidx,
+                                int32_t* cursor, uint32_t* tsum, hipStream_t s) {
+  const int64_t n = g.n, m = g.m;
+  hipError_t e = launch_fill_zero(cursor, sizeof(int32_t) * (size_t)n, s);
+  if (e != hipSuccess) return e;
+  const int bm = (int)std::min<int64_t>((m + 255) / 256, 16384);
+  const int bn = (int)std::min<int64_t>((n + 255) / 256, 16384);
+  if (m > 0) k_indeg<<<bm, 256, 0, s>>>(g.colidx, m, cursor);
+  const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  k_tile_sum<<<(unsigned)tiles, 256, 0, s>>>(cursor, n, tsum);
+  k_tile_scan<<<1, 1024, 0, s>>>(tsum, tiles);
+  // in_rowptr and the fill cursor both start as the exclusive prefix
+  k_tile_apply<<<(unsigned)tiles, 256, 0, s>>>(cursor, n, tsum, in_rowptr, cursor);
+  if (m > 0) k_fill_rev<<<bn, 256, 0, s>>>(g.rowptr, g.colidx, g.n, cursor, in_colidx);
+  return hipGetLastError();
+}
+
+hipError_t launch_list_inhubs(const int32_t* in_rowptr, int32_t n, int32_t* list, int32_t* count,
+                              int32_t cap, hipStream_t s) {
+  const int bn = (int)std::min<int64_t>((n + 255) / 256, 16384);
+  k_list_inhubs<<<bn, 256, 0, s>>>(in_rowptr, n, list, count, cap);
   return hipGetLastError();
 }
 

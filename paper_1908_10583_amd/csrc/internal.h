@@ -37,6 +37,7 @@ constexpr int kWalkChunk = 512;        // walk ids per work-queue grab
 constexpr int kStatSlots = 64;         // per-query counters are spread over slots
 constexpr int kHubDeg = 2048;          // frontier entries above this are split into pieces
 constexpr int kHubPiece = 2048;        // edges per piece of a split entry
+constexpr int kPullRatio = 16;         // default: pull a round if frontier edges * this > n + m
 constexpr double kFx = 4611686018427387904.0;  // 2^62
 
 // Error flags raised by kernels.
@@ -72,7 +73,7 @@ struct StatSlot {
   double r_sum;
   int32_t rounds;
   int32_t term_violations;
-  u64 pad;
+  u64 pull_rounds;
 };
 typedef StatSlot QueryStatsDev;
 
@@ -85,6 +86,8 @@ struct Ctrl {
   u64 hub_ctr[2];      // split frontier entries: (count << 40) | pieces, by round parity
   int32_t error;
   int32_t skip;        // set by the graph's gate when the push needs more rounds
+  int32_t npull;       // queries whose current round runs in pull mode
+  int32_t pad2;
   u64 round_size[kMaxRoundsLogged];
 };
 
@@ -96,11 +99,18 @@ struct GraphDev {
   const int2* info;
   int32_t max_deg;
   int32_t n_hubs;  // nodes with out-degree above kHubDeg
+  // reverse (in-edge) CSR for pull rounds
+  const int32_t* in_rowptr;
+  const int32_t* in_colidx;
+  int32_t n_inhubs;           // nodes with in-degree above kHubDeg, ascending
+  const int32_t* inhub_node;
+  const u64* inhub_base;      // first piece of each, exclusive prefix
+  u64 inhub_pieces;           // total pieces
 };
 
 struct Layout {
   size_t ctrl, qstats, queries, r, q, cnt, acc, pi;
-  size_t fr0, fr1, frx, hub_idx, hub_base;
+  size_t fr0, fr1, frx, hub_idx, hub_base, incd, ecnt, mode, pull_list;
   size_t plan_gi, plan_off, plan_wfx;
   size_t tile_cnt, tile_walks, tile_eoff, tile_woff;
   size_t hist, sel, cand_key, cand_id, cand_cnt, blk_ties;
@@ -124,6 +134,10 @@ struct Ws {
   float* frx;
   u64* hub_idx;   // frontier index of each split entry
   u64* hub_base;  // first piece number of each split entry
+  float* incd;    // [batch][n]: frontier increments, dense, for pull rounds
+  u64* ecnt;      // [2][batch][kStatSlots]: frontier edges per query, by round parity
+  int32_t* mode;  // [batch]: 1 if the query's current round pulls
+  int32_t* pull_list;  // queries in pull mode this round
   u64* plan_gi;
   u64* plan_off;
   u64* plan_wfx;
@@ -172,7 +186,7 @@ hipError_t launch_graph_check(const GraphDev& g, int* d_flags, int* d_maxdeg, in
                               int2* info, hipStream_t s);
 hipError_t launch_init_queries(const GraphDev& g, const Ws& w, int batch, hipStream_t s);
 hipError_t launch_push_round(const GraphDev& g, const Ws& w, const Layout& L, int batch,
-                             int t, int blocks, bool stats, int32_t* frontier_log,
+                             int t, int blocks, int pull_ratio, int32_t* frontier_log,
                              int64_t log_cap, hipStream_t s);
 hipError_t launch_plan(const GraphDev& g, const Ws& w, const Layout& L, int batch,
                        hipStream_t s);
@@ -183,6 +197,10 @@ hipError_t launch_walk_plan_from_host(const GraphDev& g, const Ws& w, int64_t en
                                       const double* d_w, hipStream_t s);
 hipError_t launch_topk(const GraphDev& g, const Ws& w, const Layout& L, int batch,
                        int kmax, int32_t* d_ids, float* d_vals, hipStream_t s);
+hipError_t launch_build_reverse(const GraphDev& g, int32_t* in_rowptr, int32_t* in_colidx,
+                                int32_t* cursor, uint32_t* tsum, hipStream_t s);
+hipError_t launch_list_inhubs(const int32_t* in_rowptr, int32_t n, int32_t* list, int32_t* count,
+                              int32_t cap, hipStream_t s);
 hipError_t launch_philox(int64_t count, const uint32_t* d_ctr, uint32_t k0, uint32_t k1,
                          uint32_t* d_out, hipStream_t s);
 

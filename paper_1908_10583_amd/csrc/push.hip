@@ -3,17 +3,23 @@
 // Round t, for every query of the batch at once:
 //   F_t = { v : r(v) > r_max * d(v) }   (kept as a queue, built by round t-1)
 //   snapshot: x_v = r(v); r(v) = 0; q(v) += alpha x_v; inc_v = (1-alpha) x_v / d(v)
-//   scatter:  r(u) += inc_v for u in N_out(v); the one increment that lifts
-//             r(u) over r_max * d(u) appends u to F_{t+1}.
-// Snapshot and scatter are separate launches, so every frontier residue is
-// read before any increment of the same round lands. The residue test is
-// made in FP64 on the FP32 residue (never a division).
+//   then r(u) += sum of inc_v over v in F_t with u in N_out(v), and every u
+//   whose residue now exceeds r_max * d(u) joins F_{t+1}.
+// The snapshot is its own launch, so every frontier residue is read before
+// any increment of the same round lands. The residue test is made in FP64
+// on the FP32 residue (never a division).
 //
-// Load balance: entries of degree <= kHubDeg are expanded per block (a block
-// takes 256 entries, scans their degrees in LDS and spreads the edges over
-// its threads). Entries of larger degree are listed by the snapshot and cut
-// into pieces of kHubPiece edges that any block may take, so a hub does not
-// hold up a round on one block.
+// The increments are applied in one of two ways, chosen per query and round:
+// * push (sparse rounds): each frontier edge does a memory-side float atomic
+//   on r(u); the increment that lifts r(u) over its threshold enqueues u.
+//   Entries of degree <= kHubDeg are expanded per block (256 entries, degrees
+//   scanned in LDS); larger ones are cut into kHubPiece-edge pieces that any
+//   block may take.
+// * pull (dense rounds, frontier edges * kPullRatio > n + m): every node sums
+//   the dense increments of its in-neighbours over the reverse graph (LDS
+//   accumulation, no atomics to HBM), then updates r(u) once and tests it.
+//   Nodes of in-degree above kHubDeg are summed in pieces by any block and
+//   added with one atomic per piece.
 #include "internal.h"
 #include "scan.h"
 
@@ -41,23 +47,21 @@ hipError_t launch_init_queries(const GraphDev& g, const Ws& w, int batch, hipStr
 }
 
 // Per-query counters are staged in LDS (dynamic: 12 bytes per query) and
-// added to the block's stat slot.
+// added to the block's stat slot and to this round's frontier-edge slot.
 __global__ __launch_bounds__(256) void k_push_snapshot(
     int t, Ctrl* ctrl, const u64* __restrict__ fr_in, float* __restrict__ frx,
-    float* __restrict__ r, float* __restrict__ q, const QueryDev* __restrict__ Q,
-    StatSlot* slots, const int2* __restrict__ info, int n, int batch, int stats,
-    int32_t* frontier_log, int64_t log_cap, u64 cap, u64* hub_idx, u64* hub_base,
-    u64 hub_cap) {
+    float* __restrict__ r, float* __restrict__ q, float* __restrict__ incd,
+    const QueryDev* __restrict__ Q, StatSlot* slots, u64* ecnt, const int2* __restrict__ info,
+    int n, int batch, int32_t* frontier_log, int64_t log_cap, u64 cap, u64* hub_idx,
+    u64* hub_base, u64 hub_cap) {
   extern __shared__ unsigned char smem[];
   u64* s_edges = (u64*)smem;
   uint32_t* s_push = (uint32_t*)(s_edges + batch);
-  if (stats) {
-    for (int i = threadIdx.x; i < batch; i += blockDim.x) {
-      s_edges[i] = 0;
-      s_push[i] = 0;
-    }
-    __syncthreads();
+  for (int i = threadIdx.x; i < batch; i += blockDim.x) {
+    s_edges[i] = 0;
+    s_push[i] = 0;
   }
+  __syncthreads();
   u64 cnt = ctrl->fr_cnt[t & 1];
   if (cnt > cap) cnt = cap;  // an overflow was already flagged by the producer
   const u64 log_base = ctrl->log_len;
@@ -76,7 +80,9 @@ __global__ __launch_bounds__(256) void k_push_snapshot(
     const double alpha = Q[b].alpha;
     q[gi] = (float)((double)q[gi] + alpha * (double)x);
     const int d = info[v].y;
-    frx[i] = (float)(((1.0 - alpha) * (double)x) / (double)d);
+    const float inc = (float)(((1.0 - alpha) * (double)x) / (double)d);
+    frx[i] = inc;
+    incd[gi] = inc;
     if (d > kHubDeg) {
       const u64 pieces = (u64)((d + kHubPiece - 1) / kHubPiece);
       const u64 old = atomicAdd(&ctrl->hub_ctr[t & 1], (1ull << 40) | pieces);
@@ -88,60 +94,209 @@ __global__ __launch_bounds__(256) void k_push_snapshot(
         atomicOr(&ctrl->error, kErrFrontierOverflow);
       }
     }
-    if (stats) {
-      atomicAdd(&s_push[b], 1u);
-      atomicAdd(&s_edges[b], (u64)d);
-    }
+    atomicAdd(&s_push[b], 1u);
+    atomicAdd(&s_edges[b], (u64)d);
     if (frontier_log) {
       const u64 pos = log_base + i;
       if (pos < (u64)log_cap) frontier_log[pos] = v;
       else atomicOr(&ctrl->error, kErrLogOverflow);
     }
   }
-  if (stats) {
-    __syncthreads();
-    const int slot = blockIdx.x & (kStatSlots - 1);
-    for (int b = threadIdx.x; b < batch; b += blockDim.x) {
-      if (s_push[b]) {
-        StatSlot* st = &slots[(size_t)b * kStatSlots + slot];
-        atomicAdd(&st->pushes, (u64)s_push[b]);
-        atomicAdd(&st->edge_ops, s_edges[b]);
-        atomicMax(&st->rounds, t + 1);
-      }
+  __syncthreads();
+  const int slot = blockIdx.x & (kStatSlots - 1);
+  u64* ec = ecnt + (size_t)(t & 1) * batch * kStatSlots;
+  for (int b = threadIdx.x; b < batch; b += blockDim.x) {
+    if (s_push[b]) {
+      StatSlot* st = &slots[(size_t)b * kStatSlots + slot];
+      atomicAdd(&st->pushes, (u64)s_push[b]);
+      atomicAdd(&st->edge_ops, s_edges[b]);
+      atomicMax(&st->rounds, t + 1);
+      atomicAdd(&ec[(size_t)b * kStatSlots + slot], s_edges[b]);
     }
   }
 }
 
-// Apply one residue increment; the increment that lifts r(u) over its
-// threshold enqueues u (staged in LDS, spilling to the global queue).
+// One block: choose pull or push for every query's round t; list the pull
+// queries; clear the next round's frontier-edge slots.
+__global__ __launch_bounds__(256) void k_push_mode(int t, Ctrl* ctrl, u64* ecnt, int32_t* mode,
+                                                   int32_t* pull_list, StatSlot* slots,
+                                                   int batch, u64 n_plus_m, int pull_ratio) {
+  __shared__ int32_t s_tmp[4];
+  const u64* ec = ecnt + (size_t)(t & 1) * batch * kStatSlots;
+  u64* ec_next = ecnt + (size_t)((t + 1) & 1) * batch * kStatSlots;
+  int32_t carry = 0;
+  for (int base = 0; base < batch; base += 256) {
+    const int b = base + threadIdx.x;
+    int32_t pull = 0;
+    if (b < batch) {
+      u64 edges = 0;
+      for (int k = 0; k < kStatSlots; ++k) edges += ec[(size_t)b * kStatSlots + k];
+      pull = (pull_ratio > 0 && edges > 0 && edges * (u64)pull_ratio > n_plus_m) ? 1 : 0;
+      mode[b] = pull;
+      if (pull) slots[(size_t)b * kStatSlots].pull_rounds += 1;
+    }
+    int32_t tot;
+    const int32_t pos = carry + block_exclusive_scan(pull, s_tmp, tot);
+    if (pull) pull_list[pos] = b;
+    carry += tot;
+  }
+  for (size_t i = threadIdx.x; i < (size_t)batch * kStatSlots; i += 256) ec_next[i] = 0;
+  if (threadIdx.x == 0) ctrl->npull = carry;
+}
+
+struct NextQueue {
+  u64* s_queue;
+  unsigned* s_qn;
+  u64* s_qbase;
+  u64* out_cnt;
+  u64* fr_out;
+  u64 cap;
+  Ctrl* ctrl;
+
+  __device__ __forceinline__ void push(u64 ent) const {
+    const unsigned slot = atomicAdd(s_qn, 1u);
+    if (slot < kQueueCap) {
+      s_queue[slot] = ent;
+    } else {
+      const u64 pos = atomicAdd(out_cnt, 1ull);
+      if (pos < cap) fr_out[pos] = ent;
+      else atomicOr(&ctrl->error, kErrFrontierOverflow);
+    }
+  }
+  // block-uniform: every thread of the block must call it
+  __device__ __forceinline__ void flush() const {
+    __syncthreads();
+    const unsigned qn = *s_qn < kQueueCap ? *s_qn : kQueueCap;
+    if (threadIdx.x == 0) *s_qbase = qn ? atomicAdd(out_cnt, (u64)qn) : 0ull;
+    __syncthreads();
+    for (unsigned k = threadIdx.x; k < qn; k += blockDim.x) {
+      const u64 pos = *s_qbase + k;
+      if (pos < cap) fr_out[pos] = s_queue[k];
+      else atomicOr(&ctrl->error, kErrFrontierOverflow);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *s_qn = 0;
+    __syncthreads();
+  }
+};
+
+// Apply one residue increment in push mode; the increment that lifts r(u)
+// over its threshold enqueues u.
 __device__ __forceinline__ void push_edge(int b, int u, float inc, double rmax,
                                           float* __restrict__ r, int n,
-                                          const int2* __restrict__ info, unsigned* s_qn,
-                                          u64* s_queue, u64* out_cnt, u64* fr_out, u64 cap,
-                                          Ctrl* ctrl) {
+                                          const int2* __restrict__ info, const NextQueue& nq) {
   const size_t gi = (size_t)b * n + u;
   const float old = unsafeAtomicAdd(&r[gi], inc);
   const float now = old + inc;
   // every threshold is at least r_max (d >= 1): cheap pre-filter
   if ((double)now > rmax) {
     const double thr = rmax * (double)info[u].y;
-    if ((double)old <= thr && (double)now > thr) {
-      const u64 ent = ((u64)b << 32) | (uint32_t)u;
-      const unsigned slot = atomicAdd(s_qn, 1u);
-      if (slot < kQueueCap) {
-        s_queue[slot] = ent;
-      } else {
-        const u64 pos = atomicAdd(out_cnt, 1ull);
-        if (pos < cap) fr_out[pos] = ent;
-        else atomicOr(&ctrl->error, kErrFrontierOverflow);
+    if ((double)old <= thr && (double)now > thr) nq.push(((u64)b << 32) | (uint32_t)u);
+  }
+}
+
+__global__ __launch_bounds__(kScatterBlock) void k_push_pull(
+    int t, Ctrl* ctrl, u64* __restrict__ fr_out, u64 cap, float* __restrict__ r,
+    const float* __restrict__ incd, const QueryDev* __restrict__ Q,
+    const int32_t* __restrict__ pull_list, const int2* __restrict__ info,
+    const int32_t* __restrict__ in_rowptr, const int32_t* __restrict__ in_colidx,
+    const int32_t* __restrict__ inhub_node, const u64* __restrict__ inhub_base, int n_inhubs,
+    u64 inhub_pieces, int n) {
+  __shared__ u64 s_pre[kScatterBlock];
+  __shared__ int32_t s_start[kScatterBlock];
+  __shared__ float s_sum[kScatterBlock];
+  __shared__ u64 s_queue[kQueueCap];
+  __shared__ unsigned s_qn;
+  __shared__ u64 s_qbase;
+  __shared__ u64 s_tmp[kScatterBlock / 64];
+  __shared__ float s_tmpf[kScatterBlock / 64];
+  (void)t;
+  const int npull = ctrl->npull;
+  if (npull == 0) return;  // uniform
+  const NextQueue nq{s_queue, &s_qn, &s_qbase, &ctrl->fr_cnt[(t + 1) & 1], fr_out, cap, ctrl};
+  if (threadIdx.x == 0) s_qn = 0;
+  __syncthreads();
+  const u64 chunks = ((u64)n + kScatterBlock - 1) / kScatterBlock;
+  const u64 per_query = chunks + inhub_pieces;
+  const u64 items = per_query * (u64)npull;
+  for (u64 it = blockIdx.x; it < items; it += gridDim.x) {
+    const int b = pull_list[it / per_query];
+    const u64 j = it % per_query;
+    const double rmax = Q[b].rmax;
+    const float* inc_row = incd + (size_t)b * n;
+    if (j < chunks) {
+      const int u0 = (int)(j * kScatterBlock);
+      const int u = u0 + (int)threadIdx.x;
+      u64 deg = 0;
+      if (u < n) {
+        const int32_t a = in_rowptr[u], c = in_rowptr[u + 1];
+        s_start[threadIdx.x] = a;
+        deg = (c - a) > kHubDeg ? 0ull : (u64)(c - a);
+      }
+      s_sum[threadIdx.x] = 0.0f;
+      u64 total;
+      const u64 pre = block_exclusive_scan(deg, s_tmp, total);
+      s_pre[threadIdx.x] = pre;
+      __syncthreads();
+      const int last = (n - u0 < kScatterBlock ? n - u0 : kScatterBlock) - 1;
+      for (u64 k = threadIdx.x; k < total; k += kScatterBlock) {
+        int lo = 0, hi = last;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pre[mid] <= k) lo = mid;
+          else hi = mid - 1;
+        }
+        const float val = inc_row[in_colidx[(int64_t)s_start[lo] + (int64_t)(k - s_pre[lo])]];
+        if (val != 0.0f) atomicAdd(&s_sum[lo], val);
+      }
+      __syncthreads();
+      if (u < n) {
+        const float add = s_sum[threadIdx.x];
+        if (add > 0.0f) {
+          const size_t gi = (size_t)b * n + u;
+          const float now = r[gi] + add;
+          r[gi] = now;
+          if ((double)now > rmax * (double)info[u].y) nq.push(((u64)b << 32) | (uint32_t)u);
+        }
+      }
+    } else {
+      // a piece of a node with large in-degree
+      const u64 p = j - chunks;
+      int lo = 0, hi = n_inhubs - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (inhub_base[mid] <= p) lo = mid;
+        else hi = mid - 1;
+      }
+      const int u = inhub_node[lo];
+      const int64_t a = in_rowptr[u], c = in_rowptr[u + 1];
+      const int64_t first = a + (int64_t)(p - inhub_base[lo]) * kHubPiece;
+      const int64_t end = first + kHubPiece < c ? first + kHubPiece : c;
+      float part = 0.0f;
+      for (int64_t k = first + threadIdx.x; k < end; k += kScatterBlock)
+        part += inc_row[in_colidx[k]];
+      const float sum = block_sum(part, s_tmpf);
+      if (threadIdx.x == 0 && sum > 0.0f) {
+        const size_t gi = (size_t)b * n + u;
+        const float old = unsafeAtomicAdd(&r[gi], sum);
+        const float now = old + sum;
+        const double thr = rmax * (double)info[u].y;
+        if ((double)old <= thr && (double)now > thr) nq.push(((u64)b << 32) | (uint32_t)u);
       }
     }
+    // flush when the LDS queue is half full (decision taken after a barrier,
+    // so it is the same for the whole block)
+    __syncthreads();
+    const bool full = s_qn > kQueueCap / 2;
+    if (full) nq.flush();
   }
+  nq.flush();
 }
 
 __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
     int t, Ctrl* ctrl, const u64* __restrict__ fr_in, const float* __restrict__ frx,
-    u64* __restrict__ fr_out, u64 cap, float* __restrict__ r, const QueryDev* __restrict__ Q,
+    u64* __restrict__ fr_out, u64 cap, float* __restrict__ r, float* __restrict__ incd,
+    const int32_t* __restrict__ mode, const QueryDev* __restrict__ Q,
     const int2* __restrict__ info, const int32_t* __restrict__ colidx, int n,
     const u64* __restrict__ hub_idx, const u64* __restrict__ hub_base, u64 hub_cap) {
   __shared__ u64 s_pre[kScatterBlock];
@@ -163,24 +318,15 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
     ctrl->log_len += cnt;
     ctrl->hub_ctr[(t + 1) & 1] = 0;
   }
-  u64* out_cnt = &ctrl->fr_cnt[(t + 1) & 1];
+  const NextQueue nq{s_queue, &s_qn, &s_qbase, &ctrl->fr_cnt[(t + 1) & 1], fr_out, cap, ctrl};
   if (threadIdx.x == 0) s_qn = 0;
+  // the dense increments were read by the pull launch; clear them
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (u64)gridDim.x * blockDim.x) {
+    const u64 e = fr_in[i];
+    incd[(size_t)(e >> 32) * n + (uint32_t)e] = 0.0f;
+  }
   __syncthreads();
-
-  auto flush = [&]() {
-    __syncthreads();
-    const unsigned qn = s_qn < kQueueCap ? s_qn : kQueueCap;
-    if (threadIdx.x == 0) s_qbase = qn ? atomicAdd(out_cnt, (u64)qn) : 0ull;
-    __syncthreads();
-    for (unsigned k = threadIdx.x; k < qn; k += kScatterBlock) {
-      const u64 pos = s_qbase + k;
-      if (pos < cap) fr_out[pos] = s_queue[k];
-      else atomicOr(&ctrl->error, kErrFrontierOverflow);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) s_qn = 0;
-    __syncthreads();
-  };
 
   // pieces of split (high-degree) entries, shared by all blocks
   const u64 total_pieces = (hubs & ((1ull << 40) - 1));
@@ -195,6 +341,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
     const u64 i = hub_idx[lo];
     const u64 e = fr_in[i];
     const int b = (int)(e >> 32);
+    if (mode[b]) continue;  // uniform per block: this query pulls this round
     const int v = (int)(uint32_t)e;
     const int2 inf = info[v];
     const float inc = frx[i];
@@ -202,17 +349,16 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
     const int64_t first = (int64_t)(p - hub_base[lo]) * kHubPiece;
     const int64_t last = first + kHubPiece < inf.y ? first + kHubPiece : inf.y;
     for (int64_t k = first + threadIdx.x; k < last; k += kScatterBlock)
-      push_edge(b, colidx[(int64_t)inf.x + k], inc, rmax, r, n, info, &s_qn, s_queue, out_cnt,
-                fr_out, cap, ctrl);
+      push_edge(b, colidx[(int64_t)inf.x + k], inc, rmax, r, n, info, nq);
     // all threads read the queue length after the barrier, so the decision
     // to flush (which contains barriers) is the same for the whole block
     __syncthreads();
     const bool full = s_qn > kQueueCap / 2;
-    if (full) flush();
+    if (full) nq.flush();
   }
-  flush();
+  nq.flush();
 
-  // entries of degree <= kHubDeg, 256 per block-chunk
+  // entries of degree <= kHubDeg of push-mode queries, 256 per block-chunk
   for (u64 base = (u64)blockIdx.x * kScatterBlock; base < cnt;
        base += (u64)gridDim.x * kScatterBlock) {
     const u64 i = base + threadIdx.x;
@@ -226,7 +372,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
       s_ent_b[threadIdx.x] = (uint32_t)b;
       s_inc[threadIdx.x] = frx[i];
       s_rmax[threadIdx.x] = Q[b].rmax;
-      deg = inf.y > kHubDeg ? 0ull : (u64)inf.y;
+      deg = (inf.y > kHubDeg || mode[b]) ? 0ull : (u64)inf.y;
     }
     u64 total;
     const u64 pre = block_exclusive_scan(deg, s_tmp, total);
@@ -234,8 +380,8 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
     __syncthreads();
     const int last = (int)((cnt - base < (u64)kScatterBlock) ? (cnt - base) : kScatterBlock) - 1;
     for (u64 k = threadIdx.x; k < total; k += kScatterBlock) {
-      // owner entry: the largest j with s_pre[j] <= k among entries of
-      // non-zero (expanded) degree
+      // owner entry: the largest j with s_pre[j] <= k; it has a non-zero
+      // expanded degree (entries of expanded degree 0 never own an edge)
       int lo = 0, hi = last;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -243,25 +389,32 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
         else hi = mid - 1;
       }
       push_edge((int)s_ent_b[lo], colidx[(int64_t)s_start[lo] + (int64_t)(k - s_pre[lo])],
-                s_inc[lo], s_rmax[lo], r, n, info, &s_qn, s_queue, out_cnt, fr_out, cap, ctrl);
+                s_inc[lo], s_rmax[lo], r, n, info, nq);
     }
-    flush();
+    nq.flush();
   }
 }
 
 hipError_t launch_push_round(const GraphDev& g, const Ws& w, const Layout& L, int batch, int t,
-                             int blocks, bool stats, int32_t* frontier_log, int64_t log_cap,
+                             int blocks, int pull_ratio, int32_t* frontier_log, int64_t log_cap,
                              hipStream_t s) {
   const int par = t & 1;
-  const size_t smem = stats ? (size_t)batch * (sizeof(u64) + sizeof(uint32_t)) : 0;
+  const size_t smem = (size_t)batch * (sizeof(u64) + sizeof(uint32_t));
   const u64 cap = (u64)L.cap;
-  k_push_snapshot<<<blocks, 256, smem, s>>>(t, w.ctrl, w.fr[par], w.frx, w.r, w.q, w.queries,
-                                            w.qstats, g.info, g.n, batch, stats ? 1 : 0,
+  k_push_snapshot<<<blocks, 256, smem, s>>>(t, w.ctrl, w.fr[par], w.frx, w.r, w.q, w.incd,
+                                            w.queries, w.qstats, w.ecnt, g.info, g.n, batch,
                                             frontier_log, log_cap, cap, w.hub_idx, w.hub_base,
                                             (u64)L.hub_cap);
+  k_push_mode<<<1, 256, 0, s>>>(t, w.ctrl, w.ecnt, w.mode, w.pull_list, w.qstats, batch,
+                                (u64)g.n + (u64)g.m, pull_ratio);
+  k_push_pull<<<blocks, kScatterBlock, 0, s>>>(t, w.ctrl, w.fr[par ^ 1], cap, w.r, w.incd,
+                                               w.queries, w.pull_list, g.info, g.in_rowptr,
+                                               g.in_colidx, g.inhub_node, g.inhub_base,
+                                               g.n_inhubs, g.inhub_pieces, g.n);
   k_push_scatter<<<blocks, kScatterBlock, 0, s>>>(t, w.ctrl, w.fr[par], w.frx, w.fr[par ^ 1],
-                                                  cap, w.r, w.queries, g.info, g.colidx, g.n,
-                                                  w.hub_idx, w.hub_base, (u64)L.hub_cap);
+                                                  cap, w.r, w.incd, w.mode, w.queries, g.info,
+                                                  g.colidx, g.n, w.hub_idx, w.hub_base,
+                                                  (u64)L.hub_cap);
   return hipGetLastError();
 }
 

@@ -36,10 +36,10 @@ class fora_stats(ctypes.Structure):
                 ("rmax", ctypes.c_double), ("omega_unit", ctypes.c_double),
                 ("t_alpha", ctypes.c_uint32), ("ms_push", ctypes.c_float),
                 ("ms_plan", ctypes.c_float), ("ms_walk", ctypes.c_float),
-                ("ms_topk", ctypes.c_float), ("reserved", ctypes.c_uint32)]
+                ("ms_topk", ctypes.c_float), ("pull_rounds", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class fora_query(ctypes.Structure):
@@ -50,7 +50,8 @@ class fora_query(ctypes.Structure):
 
 class fora_tuning(ctypes.Structure):
     _fields_ = [("walk_blocks_per_cu", ctypes.c_int32), ("walk_chunk", ctypes.c_int32),
-                ("push_blocks_per_cu", ctypes.c_int32), ("graph_rounds", ctypes.c_int32)]
+                ("push_blocks_per_cu", ctypes.c_int32), ("graph_rounds", ctypes.c_int32),
+                ("pull_ratio", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

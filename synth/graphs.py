@@ -81,6 +81,30 @@ def uniform_out_graph(n: int = 1000, d: int = 10, seed: int = 0) -> Graph:
                  params=dict(kind="uniform", n=n, d=d, seed=seed))
 
 
+def hub_graph(n: int = 8000, extra: int = 3, seed: int = 0) -> Graph:
+    """Node 0 points to every other node (out-degree n-1), every other node
+    points to node 1 (in-degree n-1 or so) and to ``extra`` random non-self
+    targets: a small graph whose frontiers hold very high-degree entries."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    src = [np.zeros(n - 1, np.int64)]
+    dst = [np.arange(1, n, dtype=np.int64)]
+    others = np.arange(2, n, dtype=np.int64)
+    src.append(others)
+    dst.append(np.ones(n - 2, np.int64))
+    for _ in range(extra):
+        t = rng.integers(0, n - 1, size=n - 1)
+        v = np.arange(1, n, dtype=np.int64)
+        t = t + (t >= v)
+        src.append(v)
+        dst.append(t)
+    s_ = np.concatenate(src)
+    d_ = np.concatenate(dst)
+    key = np.unique(s_ * n + d_)
+    rowptr, colidx = _csr_from_edges(n, key // n, key % n)
+    return Graph(rowptr, colidx, name=f"hub-n{n}-s{seed}",
+                 params=dict(kind="hub", n=n, extra=extra, seed=seed))
+
+
 def _rmat_samples(scale: int, count: int, a: float, b: float, c: float,
                   rng: np.random.Generator):
     """Draw ``count`` R-MAT (src, dst) pairs on 2^scale nodes."""
