@@ -202,6 +202,66 @@ int fora_walk_only(const fora_graph *g, int64_t entries, const int32_t *d_v,
 int fora_philox(int64_t count, const uint32_t *d_ctr, uint32_t key0,
                 uint32_t key1, uint32_t *d_out, void *stream);
 
+/* ---- learned r_max --------------------------------------------------------
+ * A small MLP predicts y = ln(r_max / r_max*) per source from 7 features; the
+ * eps guarantee (Lemma 2) holds for any r_max, so the model only moves cost
+ * between the push and the walks. Parameter vector of FORA_MLP_PARAMS floats:
+ * mu[7], sigma[7] (feature standardisation, not trained), W1[64][7], b1[64],
+ * W2[64][64], b2[64], W3[64], b3; y = W3.gelu(W2 gelu(W1 x' + b1) + b2) + b3
+ * with x' = (x - mu) / sigma and gelu(z) = z Phi(z). */
+#define FORA_MLP_FEATURES 7
+#define FORA_MLP_PARAMS 4751
+#define FORA_MLP_ACTS 128 /* floats saved per sample by the FP32 forward pass */
+/* floats of scratch for fora_mlp_backward with `count` samples */
+#define FORA_MLP_SCRATCH(count) ((size_t)(count) * 129 + ((size_t)(count) + 255) / 256)
+
+/* Features per source, float[count][7]: ln d(s); ln of the summed out-degree
+ * of s's out-neighbours; the residue mass on nodes over their threshold after
+ * the first synchronous push round at r_max* (0 if s is not pushed); ln n;
+ * ln m; alpha; eps. d_srcs int32[count], device. */
+int fora_features(const fora_graph *g, int32_t count, const int32_t *d_srcs, double alpha,
+                  double eps, double delta, double pf, float *d_features, void *stream);
+/* FP32 forward; d_acts (nullable, float[count][FORA_MLP_ACTS]) keeps what the
+ * backward pass needs. */
+int fora_mlp_forward(int32_t count, const float *d_x, const float *d_params, float *d_y,
+                     float *d_acts, void *stream);
+/* Gradient of L = mean_i (y_i - t_i)^2 with respect to the trained part of
+ * the parameters (d_grad, FORA_MLP_PARAMS floats; the mu/sigma entries are
+ * left untouched) and L itself (d_loss, 1 float). Needs the d_acts and d_y of
+ * a forward pass on the same d_x and FORA_MLP_SCRATCH(count) floats of
+ * scratch. Deterministic: sums run in sample order. */
+int fora_mlp_backward(int32_t count, const float *d_x, const float *d_params,
+                      const float *d_acts, const float *d_y, const float *d_target,
+                      float *d_grad, float *d_loss, float *d_scratch, void *stream);
+/* One Adam step (bias-corrected, step >= 1) on the trained parameters. */
+int fora_adam_step(float *d_params, const float *d_grad, float *d_m, float *d_v, float lr,
+                   float beta1, float beta2, float eps, int32_t step, void *stream);
+/* Parameters rounded to BF16 (nearest even), and the BF16 forward pass
+ * (weights, standardised inputs and hidden activations in BF16, sums FP32). */
+int fora_mlp_to_bf16(const float *d_params, uint16_t *d_params_bf16, void *stream);
+int fora_mlp_forward_bf16(int32_t count, const float *d_x, const uint16_t *d_params_bf16,
+                          float *d_y, void *stream);
+/* Features, BF16 forward and r_max = r_max* exp(y) for each source, where
+ * r_max* is eqn:rmax for (eps, delta, pf); sources whose y is not finite or
+ * lies outside [log_lo, log_hi] get r_max* (h_fallbacks, nullable, counts
+ * them and makes the call wait). d_scratch: FORA_PREDICT_SCRATCH(count)
+ * floats (features, outputs and a counter). d_rmax: double[count]. */
+#define FORA_PREDICT_SCRATCH(count) ((size_t)(count) * 8 + 1)
+int fora_predict_rmax(const fora_graph *g, int32_t count, const int32_t *d_srcs, double alpha,
+                      double eps, double delta, double pf, const uint16_t *d_params_bf16,
+                      double log_lo, double log_hi, float *d_scratch, double *d_rmax,
+                      int32_t *h_fallbacks, void *stream);
+/* Push cost at several thresholds in one pass per source: pushes to
+ * r_0 = mult[0] r_max*, then lowers the threshold to mult[1] r_max* and keeps
+ * pushing from the current state, and so on (mult strictly decreasing).
+ * After each threshold i it records the cumulative residue increments
+ * (h_edge_ops[b * nthr + i]) and the walks Algorithm 2 would then run,
+ * W = sum_v ceil(r(v) omega_unit) (h_walks[b * nthr + i]). The query's rmax
+ * field is ignored. Waits for completion. */
+int fora_push_sweep(const fora_graph *g, int32_t batch, const fora_query *h_queries,
+                    int32_t nthr, const double *h_mult, void *d_ws, size_t ws_bytes,
+                    int64_t *h_edge_ops, uint64_t *h_walks, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,7 @@ this module only marshals numpy arrays through ctypes.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -52,6 +53,8 @@ def _load():
     lib.oracle_constants.argtypes = [i64, f64, f64, f64, f64, f64, P]
     lib.oracle_push.argtypes = [i32, P, P, i32, f64, f64, P, P, i32, P, P, P, i64, P]
     lib.oracle_push.restype = i32
+    lib.oracle_push_continue.argtypes = [i32, P, P, f64, f64, P, P, i32, P, P, P, i64, P]
+    lib.oracle_push_continue.restype = i32
     lib.oracle_plan.argtypes = [i32, P, f64, P, P, P]
     lib.oracle_plan.restype = i64
     lib.oracle_walks.argtypes = [i32, P, P, u32, u32, u32, i64, P, P, P, P, P, P, P]
@@ -124,6 +127,36 @@ def push(g, s: int, alpha: float, rmax: float, max_rounds: int = 100000,
         offs = np.concatenate([[0], np.cumsum(sizes)])
         out["frontiers"] = [flog[offs[i]:offs[i + 1]].copy() for i in range(rounds)]
     return out
+
+
+def push_sweep(g, s: int, alpha: float, rmaxes, omega_unit: float,
+               max_rounds: int = 100000) -> dict:
+    """Algorithm 1 at r_max = rmaxes[0], then continued from the state it
+    left at each lower threshold in turn (the loop of Algorithm 1 only needs
+    a state, not r = e_s). After threshold i: cumulative edge operations
+    E[i] and the walk count Algorithm 2 would then run, W[i] = sum_v
+    ceil(r(v) omega_unit); min_margin is the smallest relative distance of a
+    tested residue from its threshold over the whole sweep."""
+    lib = _load()
+    rp, ci = _csr(g)
+    n = rp.shape[0] - 1
+    r = np.zeros(n, np.float64)
+    q = np.zeros(n, np.float64)
+    r[int(s)] = 1.0
+    sizes = np.zeros(max_rounds, np.int32)
+    ops = np.zeros(1, np.int64)
+    margin = np.zeros(1, np.float64)
+    E, W, total, mmin = [], [], 0, math.inf
+    for rm in rmaxes:
+        rounds = lib.oracle_push_continue(n, _p(rp), _p(ci), alpha, float(rm), _p(r), _p(q),
+                                          max_rounds, _p(sizes), _p(ops), None, 0, _p(margin))
+        if rounds < 0:
+            raise RuntimeError(f"oracle_push_continue failed ({rounds})")
+        total += int(ops[0])
+        mmin = min(mmin, float(margin[0]))
+        E.append(total)
+        W.append(int(np.ceil(r[r > 0] * omega_unit).sum()))
+    return dict(E=np.array(E, np.int64), W=np.array(W, np.int64), r=r, q=q, min_margin=mmin)
 
 
 def plan(r: np.ndarray, omega_unit: float):

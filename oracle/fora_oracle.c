@@ -125,16 +125,17 @@ void oracle_constants(int64_t m, double alpha, double eps, double delta,
 /* Returns the number of rounds, or -1 if max_rounds was exceeded, -2 if the */
 /* frontier log overflowed.                                                  */
 /* ------------------------------------------------------------------------ */
-int32_t oracle_push(int32_t n, const int32_t *rowptr, const int32_t *colidx,
-                    int32_t s, double alpha, double rmax, double *r, double *q,
-                    int32_t max_rounds, int32_t *round_sizes,
-                    int64_t *edge_ops, int32_t *frontier_log,
-                    int64_t frontier_cap, double *min_margin) {
+/* The push loop from a given (r, q), so that Algorithm 1 can be continued  */
+/* at a lower threshold from the state another threshold left.              */
+int32_t oracle_push_continue(int32_t n, const int32_t *rowptr,
+                             const int32_t *colidx, double alpha, double rmax,
+                             double *r, double *q, int32_t max_rounds,
+                             int32_t *round_sizes, int64_t *edge_ops,
+                             int32_t *frontier_log, int64_t frontier_cap,
+                             double *min_margin) {
   int32_t *front = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
   double *x = (double *)malloc(sizeof(double) * (size_t)n);
   if (!front || !x) { free(front); free(x); return -3; }
-  for (int32_t v = 0; v < n; ++v) { r[v] = 0.0; q[v] = 0.0; }
-  r[s] = 1.0;
   int32_t rounds = 0;
   int64_t ops = 0, logged = 0;
   double margin = INFINITY;
@@ -177,6 +178,19 @@ int32_t oracle_push(int32_t n, const int32_t *rowptr, const int32_t *colidx,
   free(front);
   free(x);
   return rounds;
+}
+
+/* Algorithm 1 from r = e_s, q = 0. */
+int32_t oracle_push(int32_t n, const int32_t *rowptr, const int32_t *colidx,
+                    int32_t s, double alpha, double rmax, double *r, double *q,
+                    int32_t max_rounds, int32_t *round_sizes,
+                    int64_t *edge_ops, int32_t *frontier_log,
+                    int64_t frontier_cap, double *min_margin) {
+  for (int32_t v = 0; v < n; ++v) { r[v] = 0.0; q[v] = 0.0; }
+  r[s] = 1.0;
+  return oracle_push_continue(n, rowptr, colidx, alpha, rmax, r, q, max_rounds,
+                              round_sizes, edge_ops, frontier_log,
+                              frontier_cap, min_margin);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfora.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "graph.hip", "push.hip", "plan.hip", "walk.hip", "topk.hip"]
+SOURCES = ["api.hip", "graph.hip", "push.hip", "plan.hip", "walk.hip", "topk.hip", "learned.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -778,6 +778,166 @@ int fora_walk_only(const fora_graph* gc, int64_t entries, const int32_t* d_v,
   return FORA_OK;
 }
 
+int fora_features(const fora_graph* g, int32_t count, const int32_t* d_srcs, double alpha,
+                  double eps, double delta, double pf, float* d_features, void* stream) {
+  if (!g || count < 0 || (count > 0 && (!d_srcs || !d_features)))
+    return fail(FORA_E_ARG, "bad argument");
+  fora_query q{};
+  q.src = 0;
+  q.k = 1;
+  q.alpha = alpha;
+  q.eps = eps;
+  q.delta = delta;
+  q.pf = pf;
+  const int rc = check_query(g, q);
+  if (rc != FORA_OK) return rc;
+  const QueryDev qd = plan_query(g, q);
+  FORA_HIP(launch_features(g->dev, count, d_srcs, alpha, eps, qd.rmax, d_features,
+                           (hipStream_t)stream));
+  return FORA_OK;
+}
+
+int fora_mlp_forward(int32_t count, const float* d_x, const float* d_params, float* d_y,
+                     float* d_acts, void* stream) {
+  if (count < 0 || (count > 0 && (!d_x || !d_params || !d_y)))
+    return fail(FORA_E_ARG, "bad argument");
+  FORA_HIP(launch_mlp_forward(count, d_x, d_params, d_y, d_acts, (hipStream_t)stream));
+  return FORA_OK;
+}
+
+int fora_mlp_backward(int32_t count, const float* d_x, const float* d_params,
+                      const float* d_acts, const float* d_y, const float* d_target,
+                      float* d_grad, float* d_loss, float* d_scratch, void* stream) {
+  if (count < 1 || !d_x || !d_params || !d_acts || !d_y || !d_target || !d_grad || !d_loss ||
+      !d_scratch)
+    return fail(FORA_E_ARG, "bad argument");
+  FORA_HIP(launch_mlp_backward(count, d_x, d_params, d_acts, d_y, d_target, d_grad, d_loss,
+                               d_scratch, (hipStream_t)stream));
+  return FORA_OK;
+}
+
+int fora_adam_step(float* d_params, const float* d_grad, float* d_m, float* d_v, float lr,
+                   float beta1, float beta2, float eps, int32_t step, void* stream) {
+  if (!d_params || !d_grad || !d_m || !d_v || step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f) ||
+      !(beta1 < 1.0f) || !(beta2 >= 0.0f) || !(beta2 < 1.0f) || !(eps > 0.0f))
+    return fail(FORA_E_ARG, "bad argument");
+  FORA_HIP(launch_adam(d_params, d_grad, d_m, d_v, lr, beta1, beta2, eps, step,
+                       (hipStream_t)stream));
+  return FORA_OK;
+}
+
+int fora_mlp_to_bf16(const float* d_params, uint16_t* d_params_bf16, void* stream) {
+  if (!d_params || !d_params_bf16) return fail(FORA_E_ARG, "bad argument");
+  FORA_HIP(launch_to_bf16(FORA_MLP_PARAMS, d_params, d_params_bf16, (hipStream_t)stream));
+  return FORA_OK;
+}
+
+int fora_mlp_forward_bf16(int32_t count, const float* d_x, const uint16_t* d_params_bf16,
+                          float* d_y, void* stream) {
+  if (count < 0 || (count > 0 && (!d_x || !d_params_bf16 || !d_y)))
+    return fail(FORA_E_ARG, "bad argument");
+  FORA_HIP(launch_mlp_forward_bf16(count, d_x, d_params_bf16, d_y, (hipStream_t)stream));
+  return FORA_OK;
+}
+
+int fora_predict_rmax(const fora_graph* g, int32_t count, const int32_t* d_srcs, double alpha,
+                      double eps, double delta, double pf, const uint16_t* d_params_bf16,
+                      double log_lo, double log_hi, float* d_scratch, double* d_rmax,
+                      int32_t* h_fallbacks, void* stream) {
+  if (!g || count < 0 || (count > 0 && (!d_srcs || !d_params_bf16 || !d_scratch || !d_rmax)) ||
+      !(log_lo <= log_hi))
+    return fail(FORA_E_ARG, "bad argument");
+  if (count == 0) {
+    if (h_fallbacks) *h_fallbacks = 0;
+    return FORA_OK;
+  }
+  fora_query q{};
+  q.k = 1;
+  q.alpha = alpha;
+  q.eps = eps;
+  q.delta = delta;
+  q.pf = pf;
+  int rc = check_query(g, q);
+  if (rc != FORA_OK) return rc;
+  const QueryDev qd = plan_query(g, q);
+  hipStream_t s = (hipStream_t)stream;
+  float* feat = d_scratch;
+  float* y = d_scratch + (size_t)count * FORA_MLP_FEATURES;
+  // the fallback counter follows the features and the outputs
+  int* fb = (int*)(d_scratch + (size_t)count * 8);
+  FORA_HIP(launch_fill_zero(fb, sizeof(int), s));
+  FORA_HIP(launch_features(g->dev, count, d_srcs, alpha, eps, qd.rmax, feat, s));
+  FORA_HIP(launch_mlp_forward_bf16(count, feat, d_params_bf16, y, s));
+  FORA_HIP(launch_rmax_from_output(count, y, qd.rmax, log_lo, log_hi, d_rmax, fb, s));
+  if (h_fallbacks) {
+    int v = 0;
+    FORA_HIP(hipMemcpyAsync(&v, fb, sizeof(int), hipMemcpyDeviceToHost, s));
+    FORA_HIP(hipStreamSynchronize(s));
+    *h_fallbacks = v;
+  }
+  return FORA_OK;
+}
+
+int fora_push_sweep(const fora_graph* gc, int32_t batch, const fora_query* h_queries,
+                    int32_t nthr, const double* h_mult, void* d_ws, size_t ws_bytes,
+                    int64_t* h_edge_ops, uint64_t* h_walks, void* stream) {
+  fora_graph* g = const_cast<fora_graph*>(gc);
+  hipStream_t s = (hipStream_t)stream;
+  if (!h_queries || !h_mult || !h_edge_ops || !h_walks || nthr < 1)
+    return fail(FORA_E_ARG, "bad argument");
+  for (int i = 0; i < nthr; ++i) {
+    if (!(h_mult[i] > 0.0) || !std::isfinite(h_mult[i]) || (i > 0 && !(h_mult[i] < h_mult[i - 1])))
+      return fail(FORA_E_ARG, "multipliers must be positive and strictly decreasing");
+  }
+  Call c;
+  int rc = prepare(g, batch, d_ws, ws_bytes, c);
+  if (rc != FORA_OK) return rc;
+  std::vector<QueryDev> qd(batch), base(batch);
+  for (int b = 0; b < batch; ++b) {
+    fora_query q = h_queries[b];
+    q.rmax = 0.0;
+    rc = check_query(g, q);
+    if (rc != FORA_OK) return rc;
+    base[b] = plan_query(g, q);
+  }
+  FORA_HIP(hipSetDevice(g->device));
+  // W per query lives in the top-k histogram area, unused by this call
+  u64* walks = (u64*)c.w.hist;
+  FORA_HIP(launch_fill_zero((char*)d_ws + c.L.zero_begin, c.L.zero_end - c.L.zero_begin, s));
+  int t = 0;
+  std::vector<StatSlot> slots((size_t)batch * kStatSlots);
+  std::vector<u64> w(batch);
+  for (int i = 0; i < nthr; ++i) {
+    for (int b = 0; b < batch; ++b) {
+      qd[b] = base[b];
+      qd[b].rmax = base[b].rmax * h_mult[i];
+    }
+    FORA_HIP(hipMemcpyAsync(c.w.queries, qd.data(), sizeof(QueryDev) * batch,
+                            hipMemcpyHostToDevice, s));
+    if (i == 0) FORA_HIP(launch_init_queries(g->dev, c.w, batch, s));
+    else FORA_HIP(launch_seed_frontier(g->dev, c.w, c.L, batch, t, s));
+    int rounds = 0;
+    rc = run_push(g, c, batch, s, true, nullptr, 0, &rounds, t);
+    if (rc != FORA_OK) return rc;
+    t = rounds;
+    FORA_HIP(launch_fill_zero(walks, sizeof(u64) * batch, s));
+    FORA_HIP(launch_count_walks(g->dev, c.w, c.L, batch, walks, s));
+    FORA_HIP(hipMemcpyAsync(w.data(), walks, sizeof(u64) * batch, hipMemcpyDeviceToHost, s));
+    FORA_HIP(hipMemcpyAsync(slots.data(), c.w.qstats, sizeof(StatSlot) * slots.size(),
+                            hipMemcpyDeviceToHost, s));
+    FORA_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < batch; ++b) {
+      int64_t e = 0;
+      for (int k = 0; k < kStatSlots; ++k) e += (int64_t)slots[(size_t)b * kStatSlots + k].edge_ops;
+      h_edge_ops[(size_t)b * nthr + i] = e;
+      h_walks[(size_t)b * nthr + i] = w[b];
+    }
+  }
+  int flags = 0;
+  FORA_HIP(hipMemcpy(&flags, &c.w.ctrl->error, sizeof(int), hipMemcpyDeviceToHost));
+  return error_code_from_flags(flags);
+}
+
 int fora_philox(int64_t count, const uint32_t* d_ctr, uint32_t key0, uint32_t key1,
                 uint32_t* d_out, void* stream) {
   if (count < 0) return fail(FORA_E_ARG, "count < 0");

@@ -201,6 +201,24 @@ hipError_t launch_build_reverse(const GraphDev& g, int32_t* in_rowptr, int32_t* 
                                 int32_t* cursor, uint32_t* tsum, hipStream_t s);
 hipError_t launch_list_inhubs(const int32_t* in_rowptr, int32_t n, int32_t* list, int32_t* count,
                               int32_t cap, hipStream_t s);
+hipError_t launch_seed_frontier(const GraphDev& g, const Ws& w, const Layout& L, int batch, int t,
+                                hipStream_t s);
+hipError_t launch_count_walks(const GraphDev& g, const Ws& w, const Layout& L, int batch,
+                              u64* walks, hipStream_t s);
+hipError_t launch_features(const GraphDev& g, int count, const int32_t* srcs, double alpha,
+                           double eps, double rmax, float* out, hipStream_t s);
+hipError_t launch_mlp_forward(int count, const float* x, const float* params, float* y,
+                              float* acts, hipStream_t s);
+hipError_t launch_mlp_backward(int count, const float* x, const float* params, const float* acts,
+                               const float* y, const float* target, float* grad, float* loss,
+                               float* scratch, hipStream_t s);
+hipError_t launch_adam(float* params, const float* grad, float* m, float* v, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t s);
+hipError_t launch_to_bf16(int count, const float* in, uint16_t* out, hipStream_t s);
+hipError_t launch_mlp_forward_bf16(int count, const float* x, const uint16_t* pb, float* y,
+                                   hipStream_t s);
+hipError_t launch_rmax_from_output(int count, const float* y, double rmax_star, double lo,
+                                   double hi, double* out, int* fallbacks, hipStream_t s);
 hipError_t launch_philox(int64_t count, const uint32_t* d_ctr, uint32_t k0, uint32_t k1,
                          uint32_t* d_out, hipStream_t s);
 

@@ -173,6 +173,34 @@ hipError_t launch_push_gate(const Ws& w, int rounds, hipStream_t s) {
   return hipGetLastError();
 }
 
+// W per query for the current residues (no plan written): sum over v of
+// ceil(r(v) * omega_unit).
+__global__ __launch_bounds__(kPlanThreads) void k_count_walks(const float* __restrict__ r,
+                                                              const QueryDev* __restrict__ Q,
+                                                              int n, u64* walks) {
+  __shared__ u64 s_tmp[kPlanThreads / 64];
+  const int b = blockIdx.y;
+  const double wu = Q[b].omega_unit;
+  const float* row = r + (size_t)b * n;
+  u64 acc = 0;
+  for (int k = threadIdx.x; k < kPlanTile; k += kPlanThreads) {
+    const int v = blockIdx.x * kPlanTile + k;
+    if (v < n) {
+      const float rv = row[v];
+      if (rv > 0.0f) acc += (u64)ceil((double)rv * wu);
+    }
+  }
+  const u64 t = block_sum(acc, s_tmp);
+  if (threadIdx.x == 0 && t) atomicAdd(&walks[b], t);
+}
+
+hipError_t launch_count_walks(const GraphDev& g, const Ws& w, const Layout& L, int batch,
+                              u64* walks, hipStream_t s) {
+  dim3 grid((unsigned)L.tiles_per_row, (unsigned)batch);
+  k_count_walks<<<grid, kPlanThreads, 0, s>>>(w.r, w.queries, g.n, walks);
+  return hipGetLastError();
+}
+
 // ---- a caller-given plan (walk phase on its own) ---------------------------
 // Entries (v, omega, w) for query 0: tile sums of omega, scan, then offsets.
 __global__ __launch_bounds__(kPlanThreads) void k_hplan_count(const uint64_t* omega,

@@ -395,6 +395,45 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
   }
 }
 
+// Frontier from scratch: every (query, node) whose residue exceeds the
+// query's current threshold (used when a threshold is lowered mid-way).
+__global__ __launch_bounds__(256) void k_seed_frontier(int t, Ctrl* ctrl,
+                                                       const float* __restrict__ r,
+                                                       const QueryDev* __restrict__ Q,
+                                                       const int2* __restrict__ info, int n,
+                                                       int batch, u64* fr, u64 cap) {
+  const u64 total = (u64)batch * (u64)n;
+  const int lane = threadIdx.x & 63;
+  for (u64 base = (u64)blockIdx.x * blockDim.x; base < total; base += (u64)gridDim.x * blockDim.x) {
+    const u64 gi = base + threadIdx.x;
+    bool over = false;
+    int b = 0, v = 0;
+    if (gi < total) {
+      b = (int)(gi / (u64)n);
+      v = (int)(gi - (u64)b * n);
+      over = (double)r[gi] > Q[b].rmax * (double)info[v].y;
+    }
+    const u64 mask = __ballot(over);
+    u64 pos0 = 0;
+    if (lane == 0 && mask) pos0 = atomicAdd(&ctrl->fr_cnt[t & 1], (u64)__popcll(mask));
+    pos0 = __shfl(pos0, 0, 64);
+    if (over) {
+      const u64 pos = pos0 + lane_rank(mask);
+      if (pos < cap) fr[pos] = ((u64)b << 32) | (uint32_t)v;
+      else atomicOr(&ctrl->error, kErrFrontierOverflow);
+    }
+  }
+}
+
+hipError_t launch_seed_frontier(const GraphDev& g, const Ws& w, const Layout& L, int batch, int t,
+                                hipStream_t s) {
+  const u64 total = (u64)batch * (u64)g.n;
+  const int blocks = (int)std::min<u64>((total + 255) / 256, 16384);
+  k_seed_frontier<<<blocks, 256, 0, s>>>(t, w.ctrl, w.r, w.queries, g.info, g.n, batch,
+                                         w.fr[t & 1], (u64)L.cap);
+  return hipGetLastError();
+}
+
 hipError_t launch_push_round(const GraphDev& g, const Ws& w, const Layout& L, int batch, int t,
                              int blocks, int pull_ratio, int32_t* frontier_log, int64_t log_cap,
                              hipStream_t s) {

@@ -90,6 +90,17 @@ def _load():
         "fora_walk_only": ([P, I64, P, P, P, U32, U32, F64, P, SZ, ctypes.POINTER(U64), P],
                            ctypes.c_int),
         "fora_philox": ([I64, P, U32, U32, P, P], ctypes.c_int),
+        "fora_features": ([P, I32, P, F64, F64, F64, F64, P, P], ctypes.c_int),
+        "fora_mlp_forward": ([I32, P, P, P, P, P], ctypes.c_int),
+        "fora_mlp_backward": ([I32, P, P, P, P, P, P, P, P, P], ctypes.c_int),
+        "fora_adam_step": ([P, P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                            ctypes.c_float, I32, P], ctypes.c_int),
+        "fora_mlp_to_bf16": ([P, P, P], ctypes.c_int),
+        "fora_mlp_forward_bf16": ([I32, P, P, P, P], ctypes.c_int),
+        "fora_predict_rmax": ([P, I32, P, F64, F64, F64, F64, P, F64, F64, P, P,
+                               ctypes.POINTER(I32), P], ctypes.c_int),
+        "fora_push_sweep": ([P, I32, ctypes.POINTER(fora_query), I32, P, P, SZ, P, P, P],
+                            ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -103,7 +114,21 @@ _lib = _load()
 EXPORTED = ["fora_last_error", "fora_build_csr", "fora_free_graph", "fora_graph_info",
             "fora_get_tuning", "fora_set_tuning",
             "fora_workspace_size", "fora_workspace_views", "fora_ssppr", "fora_ssppr_batch",
-            "fora_push_only", "fora_walk_only", "fora_philox"]
+            "fora_push_only", "fora_walk_only", "fora_philox", "fora_features",
+            "fora_mlp_forward", "fora_mlp_backward", "fora_adam_step", "fora_mlp_to_bf16",
+            "fora_mlp_forward_bf16", "fora_predict_rmax", "fora_push_sweep"]
+
+FORA_MLP_FEATURES = 7
+FORA_MLP_PARAMS = 4751
+FORA_MLP_ACTS = 128
+
+
+def FORA_MLP_SCRATCH(count: int) -> int:
+    return count * 129 + (count + 255) // 256
+
+
+def FORA_PREDICT_SCRATCH(count: int) -> int:
+    return count * 8 + 1
 
 
 def _check(rc: int):
@@ -319,3 +344,77 @@ def fora_philox(ctr: np.ndarray, key, device="cuda", stream=None) -> np.ndarray:
     _check(_lib.fora_philox(c.shape[0], _ptr(dc), int(key[0]) & 0xFFFFFFFF,
                             int(key[1]) & 0xFFFFFFFF, _ptr(out), ctypes.c_void_p(_stream(stream))))
     return out.cpu().numpy().view(np.uint32)
+
+
+# ---- learned r_max --------------------------------------------------------------
+def _s(stream):
+    return ctypes.c_void_p(_stream(stream))
+
+
+def fora_features(g: Graph, srcs: torch.Tensor, alpha: float, eps: float, delta: float,
+                  pf: float, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    srcs = srcs.to(device=g.device, dtype=torch.int32).contiguous()
+    out = torch.empty((srcs.numel(), FORA_MLP_FEATURES), dtype=torch.float32,
+                      device=g.device) if out is None else out
+    _check(_lib.fora_features(g.handle, srcs.numel(), _ptr(srcs), alpha, eps, delta, pf,
+                              _ptr(out), _s(stream)))
+    return out
+
+
+def fora_mlp_forward(x: torch.Tensor, params: torch.Tensor, acts: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+    y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+    _check(_lib.fora_mlp_forward(x.shape[0], _ptr(x), _ptr(params), _ptr(y), _ptr(acts),
+                                 _s(stream)))
+    return y
+
+
+def fora_mlp_backward(x, params, acts, y, target, grad, loss, scratch, stream=None):
+    _check(_lib.fora_mlp_backward(x.shape[0], _ptr(x), _ptr(params), _ptr(acts), _ptr(y),
+                                  _ptr(target), _ptr(grad), _ptr(loss), _ptr(scratch),
+                                  _s(stream)))
+
+
+def fora_adam_step(params, grad, m, v, lr, beta1, beta2, eps, step, stream=None):
+    _check(_lib.fora_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), lr, beta1, beta2,
+                               eps, step, _s(stream)))
+
+
+def fora_mlp_to_bf16(params: torch.Tensor, stream=None) -> torch.Tensor:
+    out = torch.empty(FORA_MLP_PARAMS, dtype=torch.int16, device=params.device)
+    _check(_lib.fora_mlp_to_bf16(_ptr(params), _ptr(out), _s(stream)))
+    return out
+
+
+def fora_mlp_forward_bf16(x: torch.Tensor, params_bf16: torch.Tensor, stream=None):
+    y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+    _check(_lib.fora_mlp_forward_bf16(x.shape[0], _ptr(x), _ptr(params_bf16), _ptr(y),
+                                      _s(stream)))
+    return y
+
+
+def fora_predict_rmax(g: Graph, srcs: torch.Tensor, params_bf16: torch.Tensor, alpha: float,
+                      eps: float, delta: float, pf: float, log_lo: float, log_hi: float,
+                      stream=None):
+    srcs = srcs.to(device=g.device, dtype=torch.int32).contiguous()
+    n = srcs.numel()
+    scratch = torch.empty(FORA_PREDICT_SCRATCH(n), dtype=torch.float32, device=g.device)
+    rmax = torch.empty(n, dtype=torch.float64, device=g.device)
+    fb = ctypes.c_int32()
+    _check(_lib.fora_predict_rmax(g.handle, n, _ptr(srcs), alpha, eps, delta, pf,
+                                  _ptr(params_bf16), log_lo, log_hi, _ptr(scratch), _ptr(rmax),
+                                  ctypes.byref(fb), _s(stream)))
+    return rmax, fb.value
+
+
+def fora_push_sweep(g: Graph, queries, mults, ws: torch.Tensor | None = None, stream=None):
+    B = len(queries)
+    mults = np.ascontiguousarray(mults, np.float64)
+    ws = workspace(g, B) if ws is None else ws
+    e = np.zeros((B, mults.size), np.int64)
+    w = np.zeros((B, mults.size), np.uint64)
+    _check(_lib.fora_push_sweep(g.handle, B, queries, mults.size,
+                                mults.ctypes.data_as(ctypes.c_void_p), _ptr(ws), ws.numel(),
+                                e.ctypes.data_as(ctypes.c_void_p),
+                                w.ctypes.data_as(ctypes.c_void_p), _s(stream)))
+    return e, w

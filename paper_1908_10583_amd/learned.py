@@ -1,0 +1,277 @@
+"""Learned per-source r_max.
+
+For each training source the library pushes once through 12 thresholds
+r_i = mult_i * r_max* (mult from 8 down to 1/4, log-spaced; each threshold
+continues from the previous one's state) and records the exact push work
+E_i (residue increments) and the walk count W_i Algorithm 2 would then run.
+Costs are priced with per-unit push and walk times measured on this GPU
+(full FORA calls at several r_max, timed by the library's phase events), so
+label(s) = ln(mult of the cheapest threshold). A 7 -> 64 -> 64 -> 1 GELU MLP
+is trained on (features, label) with the library's own forward, backward and
+Adam kernels; inference runs the library's BF16 kernel, which maps the
+output y to r_max = r_max* exp(y) and falls back to r_max* for outputs that
+are not finite or leave the trained range. Since Lemma 2 holds for any
+r_max, the eps guarantee is unaffected; only cost changes.
+"""
+from __future__ import annotations
+
+import json
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import fora
+
+MULTS = np.exp(np.linspace(math.log(8.0), math.log(0.25), 12))  # descending
+LOG_LO, LOG_HI = math.log(0.25), math.log(8.0)
+
+
+def features(G, srcs, alpha=0.2, eps=0.5, delta=None, pf=None):
+    delta = 1.0 / G.n if delta is None else delta
+    pf = 1.0 / G.n if pf is None else pf
+    return fora.fora_features(G, torch.as_tensor(np.asarray(srcs), dtype=torch.int32),
+                              alpha, eps, delta, pf)
+
+
+def sweep(G, srcs, alpha=0.2, eps=0.5, delta=None, pf=None, batch=64, log=None):
+    """Push work E[s, i] and walk counts W[s, i] at every threshold of MULTS."""
+    srcs = np.asarray(srcs)
+    E = np.zeros((len(srcs), len(MULTS)), np.int64)
+    W = np.zeros((len(srcs), len(MULTS)), np.uint64)
+    ws = fora.workspace(G, batch)
+    t0 = time.perf_counter()
+    for i in range(0, len(srcs), batch):
+        part = srcs[i:i + batch]
+        qs = fora.make_queries(part, alpha=alpha, eps=eps, delta=delta, pf=pf, k=1, n=G.n)
+        e, w = fora.fora_push_sweep(G, qs, MULTS, ws=ws)
+        E[i:i + len(part)] = e
+        W[i:i + len(part)] = w
+        if log and (i // batch) % 20 == 0:
+            log(f"sweep {i + len(part)}/{len(srcs)} ({time.perf_counter() - t0:.1f}s)")
+    return E, W
+
+
+def calibrate(G, srcs, alpha=0.2, eps=0.5, mults=(0.25, 1.0, 8.0), batch=64):
+    """Per-unit costs measured on this GPU: ms per residue increment (push)
+    and ms per walk, from batched FORA calls at several r_max multipliers."""
+    srcs = np.asarray(srcs)[:batch]
+    ws = fora.workspace(G, len(srcs))
+    push_ms = walk_ms = 0.0
+    E = W = 0
+    fora.fora_ssppr_batch(G, fora.make_queries(srcs, alpha=alpha, eps=eps, k=1, n=G.n), ws=ws)
+    c = fora.fora_ssppr_batch(G, fora.make_queries(srcs[:1], alpha=alpha, eps=eps, k=1, n=G.n),
+                              ws=ws, stats=True).stats[0]
+    rstar = c["rmax"]
+    for mlt in mults:
+        qs = fora.make_queries(srcs, alpha=alpha, eps=eps, k=1, n=G.n, rmax=rstar * mlt)
+        st = fora.fora_ssppr_batch(G, qs, ws=ws, stats=True).stats
+        push_ms += st[0]["ms_push"]
+        walk_ms += st[0]["ms_walk"]
+        E += sum(s["edge_ops"] for s in st)
+        W += sum(s["walks"] for s in st)
+    return dict(ms_per_edge_op=push_ms / max(E, 1), ms_per_walk=walk_ms / max(W, 1),
+                rmax_star=rstar)
+
+
+def labels(E, W, cost):
+    total = cost["ms_per_edge_op"] * E.astype(np.float64) + \
+        cost["ms_per_walk"] * W.astype(np.float64)
+    best = np.argmin(total, axis=1)
+    return np.log(MULTS[best]), total
+
+
+class Model:
+    """MLP parameters on the device (FP32 master copy, BF16 inference copy)."""
+
+    def __init__(self, params: torch.Tensor):
+        self.params = params
+
+    @classmethod
+    def init(cls, X: np.ndarray, seed=0, device="cuda"):
+        rng = np.random.default_rng(seed)
+        p = np.zeros(fora.FORA_MLP_PARAMS, np.float32)
+        X = np.asarray(X, np.float64)
+        mu = X.mean(0)
+        sd = X.std(0)
+        # features constant over the training set (ln n, ln m, alpha, eps on
+        # one graph) keep sigma = 1: a tiny sigma would blow up the BF16
+        # rounding of mu at inference
+        sd[sd < 1e-3 * np.maximum(1.0, np.abs(mu))] = 1.0
+        p[0:7], p[7:14] = mu, sd
+        o = 14
+        for fan_in, fan_out in ((7, 64), (64, 64), (64, 1)):
+            lim = math.sqrt(6.0 / (fan_in + fan_out))
+            p[o:o + fan_in * fan_out] = rng.uniform(-lim, lim, fan_in * fan_out)
+            o += fan_in * fan_out + fan_out  # biases stay 0
+        return cls(torch.from_numpy(p).to(device))
+
+    def train(self, X, y, epochs=300, lr=3e-3, batch=1024, seed=0, log=None):
+        dev = self.params.device
+        Xt = torch.as_tensor(np.asarray(X, np.float32), device=dev)
+        yt = torch.as_tensor(np.asarray(y, np.float32), device=dev)
+        N = Xt.shape[0]
+        m = torch.zeros_like(self.params)
+        v = torch.zeros_like(self.params)
+        grad = torch.zeros_like(self.params)
+        loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        acts = torch.empty((batch, fora.FORA_MLP_ACTS), dtype=torch.float32, device=dev)
+        scratch = torch.empty(fora.FORA_MLP_SCRATCH(batch), dtype=torch.float32, device=dev)
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        step = 0
+        hist = []
+        for ep in range(epochs):
+            perm = torch.randperm(N, generator=g).to(dev)
+            tot = 0.0
+            for i in range(0, N - batch + 1 if N >= batch else 1, batch):
+                idx = perm[i:i + batch]
+                xb = Xt[idx].contiguous()
+                yb = yt[idx].contiguous()
+                yp = fora.fora_mlp_forward(xb, self.params, acts[:xb.shape[0]])
+                fora.fora_mlp_backward(xb, self.params, acts[:xb.shape[0]], yp, yb, grad, loss,
+                                       scratch)
+                step += 1
+                fora.fora_adam_step(self.params, grad, m, v, lr, 0.9, 0.999, 1e-8, step)
+                tot += float(loss.item()) if (i == 0) else 0.0
+            hist.append(tot)
+            if log and ep % 50 == 0:
+                log(f"epoch {ep}: batch loss {tot:.4f}")
+        return hist
+
+    def mse(self, X, y):
+        Xt = torch.as_tensor(np.asarray(X, np.float32), device=self.params.device)
+        yp = fora.fora_mlp_forward(Xt, self.params).cpu().numpy()
+        return float(np.mean((yp - np.asarray(y)) ** 2))
+
+    def bf16(self):
+        return fora.fora_mlp_to_bf16(self.params)
+
+    def predict_rmax(self, G, srcs, alpha=0.2, eps=0.5, delta=None, pf=None):
+        delta = 1.0 / G.n if delta is None else delta
+        pf = 1.0 / G.n if pf is None else pf
+        return fora.fora_predict_rmax(G, torch.as_tensor(np.asarray(srcs), dtype=torch.int32),
+                                      self.bf16(), alpha, eps, delta, pf, LOG_LO, LOG_HI)
+
+    def save(self, path):
+        with open(path, "w") as f:
+            json.dump(dict(params=self.params.cpu().numpy().tolist()), f)
+
+    @classmethod
+    def load(cls, path, device="cuda"):
+        with open(path) as f:
+            p = np.asarray(json.load(f)["params"], np.float32)
+        return cls(torch.from_numpy(p).to(device))
+
+
+def time_queries(G, srcs, rmax=None, alpha=0.2, eps=0.5, k=500):
+    """Per-query wall time (ms) of single fora_ssppr calls."""
+    ws = fora.workspace(G, 1)
+    out = (torch.empty(k, dtype=torch.int32, device=G.device),
+           torch.empty(k, dtype=torch.float32, device=G.device))
+    fora.fora_ssppr(G, int(srcs[0]), alpha, eps, k=k, ws=ws, out=out)
+    t = np.zeros(len(srcs))
+    for i, s in enumerate(srcs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fora.fora_ssppr(G, int(s), alpha, eps, k=k, ws=ws, out=out,
+                        rmax=None if rmax is None else float(rmax[i]))
+        torch.cuda.synchronize()
+        t[i] = (time.perf_counter() - t0) * 1e3
+    return t
+
+
+def time_batched(G, srcs, rmax=None, alpha=0.2, eps=0.5, k=500, batch=128):
+    """Queries per second of batched calls over all sources."""
+    ws = fora.workspace(G, batch)
+    total = 0.0
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(0, len(srcs), batch):
+            part = srcs[i:i + batch]
+            rm = None if rmax is None else rmax[i:i + batch]
+            qs = fora.make_queries(part, alpha=alpha, eps=eps, k=k, n=G.n, rmax=rm)
+            fora.fora_ssppr_batch(G, qs, ws=ws)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0  # keep the second (warm) pass
+    return len(srcs) / total
+
+
+def main(argv=None):
+    """Train on a workload's training sources and evaluate on its held-out
+    sources against the fixed eqn:rmax rule; prints one JSON report."""
+    import argparse
+    import sys
+
+    import synth
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="rmat22")
+    ap.add_argument("--train", type=int, default=20000)
+    ap.add_argument("--heldout", type=int, default=2048)
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--timed", type=int, default=512, help="held-out sources timed one by one")
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print(f"[learned] {msg}", file=sys.stderr, flush=True)
+
+    g, srcs = synth.workload(args.workload)
+    G = fora.Graph.from_numpy(g.rowptr, g.colidx)
+    tr, ho = srcs[:args.train], srcs[-args.heldout:]
+    log(f"graph {g.name} n={g.n} m={g.m}; train {len(tr)} held-out {len(ho)}")
+    t0 = time.perf_counter()
+    cost = calibrate(G, tr)
+    log(f"unit costs {cost}")
+    E, W = sweep(G, tr, log=log)
+    t_sweep = time.perf_counter() - t0
+    y, _ = labels(E, W, cost)
+    X = features(G, tr).cpu().numpy()
+    model = Model.init(X, seed=0)
+    t1 = time.perf_counter()
+    model.train(X, y, epochs=args.epochs, log=log)
+    t_train = time.perf_counter() - t1
+    Eh, Wh = sweep(G, ho)
+    yh, cost_h = labels(Eh, Wh, cost)
+    Xh = features(G, ho).cpu().numpy()
+    rmax_l, fallbacks = model.predict_rmax(G, ho)
+    rmax_l = rmax_l.cpu().numpy()
+    rstar = cost["rmax_star"]
+    # modelled cost on the held-out sweep (nearest grid point of the prediction)
+    pick = np.abs(np.log(rmax_l / rstar)[:, None] - np.log(MULTS)[None, :]).argmin(1)
+    i_star = np.abs(np.log(MULTS)).argmin()
+    mod_learned = cost_h[np.arange(len(ho)), pick]
+    mod_fixed = cost_h[:, i_star]
+    timed = ho[:args.timed]
+    t_fixed = time_queries(G, timed)
+    t_learn = time_queries(G, timed, rmax=rmax_l[:args.timed])
+    qps_fixed = time_batched(G, ho)
+    qps_learn = time_batched(G, ho, rmax=rmax_l)
+    t_inf0 = time.perf_counter()
+    model.predict_rmax(G, ho)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t_inf0
+    rep = dict(workload=args.workload, n=g.n, m=g.m, train=len(tr), heldout=len(ho),
+               grid=MULTS.tolist(), unit_costs=cost,
+               label_mult_histogram=np.bincount(np.argmin(np.abs(y[:, None] - np.log(MULTS)), 1),
+                                                minlength=len(MULTS)).tolist(),
+               train_mse=model.mse(X, y), heldout_mse=model.mse(Xh, yh),
+               heldout_mse_fixed_rule=float(np.mean(yh ** 2)),
+               fallbacks=fallbacks,
+               modelled_cost_ms=dict(fixed_mean=float(mod_fixed.mean()),
+                                     learned_mean=float(mod_learned.mean()),
+                                     oracle_best_mean=float(cost_h.min(1).mean())),
+               measured_single_query_ms=dict(
+                   sources=int(len(timed)),
+                   fixed_mean=float(t_fixed.mean()), fixed_p95=float(np.percentile(t_fixed, 95)),
+                   learned_mean=float(t_learn.mean()),
+                   learned_p95=float(np.percentile(t_learn, 95))),
+               batched_queries_per_s=dict(fixed=qps_fixed, learned=qps_learn),
+               sweep_seconds=t_sweep, train_seconds=t_train,
+               inference_us_per_source=t_inf / len(ho) * 1e6)
+    print(json.dumps(rep), flush=True)
+    return rep
+
+
+if __name__ == "__main__":
+    main()

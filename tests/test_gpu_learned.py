@@ -1,0 +1,192 @@
+"""Learned r_max on the GPU: features, MLP forward/backward/Adam and BF16
+inference against the FP64 reference, r_max mapping and fallback, the
+incremental push sweep, training, and the eps guarantee at learned r_max."""
+import math
+
+import numpy as np
+import pytest
+import scipy.stats as st
+
+import oracle
+import synth
+from oracle import exact, mlp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1908_10583_amd import fora, learned  # noqa: E402
+
+
+def _params(seed=0, scale=0.3):
+    rng = np.random.default_rng(seed)
+    p = rng.normal(0, scale, mlp.NPARAMS)
+    p[mlp.MU:mlp.MU + 7] = rng.normal(0, 1, 7)
+    p[mlp.SIG:mlp.SIG + 7] = rng.uniform(0.5, 2.0, 7)
+    return p.astype(np.float32)
+
+
+def _dev(a, dt=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def grmat():
+    return synth.rmat_graph(12, seed=12, cache=False)
+
+
+@pytest.fixture(scope="module")
+def Grmat(grmat):
+    return fora.Graph.from_numpy(grmat.rowptr, grmat.colidx)
+
+
+def test_features_match_reference(grmat, Grmat):
+    srcs = np.concatenate([[int(np.argmax(grmat.degrees()))], np.arange(0, 4096, 37)])
+    n = grmat.n
+    got = fora.fora_features(Grmat, _dev(srcs, torch.int32), 0.2, 0.5, 1 / n, 1 / n).cpu().numpy()
+    rstar = oracle.constants(grmat.m, 0.2, 0.5, 1 / n, 1 / n)["rmax"]
+    want = mlp.features(grmat, srcs, 0.2, 0.5, rstar)
+    np.testing.assert_allclose(got, want, rtol=2e-6, atol=1e-7)
+    assert np.count_nonzero(want[:, 2]) > 0  # the residue-mass feature is exercised
+
+
+def test_forward_backward_adam_match_reference():
+    rng = np.random.default_rng(5)
+    N = 700  # several blocks and a ragged tail
+    p = _params(5)
+    X = rng.normal(0, 1.5, (N, 7)).astype(np.float32)
+    t = rng.normal(0, 1, N).astype(np.float32)
+    dp, dX, dt_ = _dev(p), _dev(X), _dev(t)
+    acts = torch.empty((N, fora.FORA_MLP_ACTS), dtype=torch.float32, device="cuda")
+    y = fora.fora_mlp_forward(dX, dp, acts).cpu().numpy()
+    y_ref, cache = mlp.forward(p.astype(np.float64), X)
+    np.testing.assert_allclose(y, y_ref, rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(acts.cpu().numpy()[:, :64], cache["z1"], rtol=1e-5, atol=1e-5)
+    grad = torch.zeros(fora.FORA_MLP_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    scratch = torch.empty(fora.FORA_MLP_SCRATCH(N), dtype=torch.float32, device="cuda")
+    fora.fora_mlp_backward(dX, dp, acts, _dev(y), dt_, grad, loss, scratch)
+    g = grad.cpu().numpy()
+    g_ref = mlp.backward(p.astype(np.float64), X, t)
+    scale = np.abs(g_ref).max()
+    np.testing.assert_allclose(g[mlp.TRAIN0:], g_ref[mlp.TRAIN0:], rtol=1e-4, atol=1e-5 * scale)
+    assert float(loss.item()) == pytest.approx(mlp.loss(p.astype(np.float64), X, t), rel=1e-5)
+    # deterministic: a second backward pass gives identical bits
+    grad2 = torch.zeros_like(grad)
+    fora.fora_mlp_backward(dX, dp, acts, _dev(y), dt_, grad2, loss, scratch)
+    assert torch.equal(grad, grad2)
+    m = torch.zeros_like(grad)
+    v = torch.zeros_like(grad)
+    p_ref, m_ref, v_ref = mlp.adam(p.astype(np.float64), g.astype(np.float64),
+                                   np.zeros(mlp.NPARAMS), np.zeros(mlp.NPARAMS),
+                                   1e-3, 0.9, 0.999, 1e-8, 1)
+    fora.fora_adam_step(dp, grad, m, v, 1e-3, 0.9, 0.999, 1e-8, 1)
+    np.testing.assert_allclose(dp.cpu().numpy(), p_ref, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(m.cpu().numpy(), m_ref, rtol=1e-6, atol=1e-9)
+
+
+def test_bf16_inference_matches_reference():
+    rng = np.random.default_rng(6)
+    p = _params(6)
+    X = rng.normal(0, 1.5, (300, 7)).astype(np.float32)
+    pb = fora.fora_mlp_to_bf16(_dev(p))
+    got_bits = pb.cpu().numpy().view(np.uint16)
+    want_bits = (mlp.bf16_round(p).view(np.uint32) >> 16).astype(np.uint16)
+    assert np.array_equal(got_bits, want_bits)
+    y = fora.fora_mlp_forward_bf16(_dev(X), pb).cpu().numpy()
+    y_ref = mlp.forward_bf16(p, X)
+    np.testing.assert_allclose(y, y_ref, rtol=2e-2, atol=2e-2)
+    y32 = mlp.forward(p.astype(np.float64), X)[0]
+    assert np.abs(y - y32).max() < 0.2  # BF16 stays close to FP32
+
+
+def test_predict_rmax_mapping_and_fallback(grmat, Grmat):
+    n = grmat.n
+    srcs = np.arange(0, 2000, 7)
+    rstar = oracle.constants(grmat.m, 0.2, 0.5, 1 / n, 1 / n)["rmax"]
+    p = _params(7, scale=0.05)
+    pb = fora.fora_mlp_to_bf16(_dev(p))
+    X = fora.fora_features(Grmat, _dev(srcs, torch.int32), 0.2, 0.5, 1 / n, 1 / n)
+    y = fora.fora_mlp_forward_bf16(X, pb).cpu().numpy().astype(np.float64)
+    rm, fb = fora.fora_predict_rmax(Grmat, _dev(srcs, torch.int32), pb, 0.2, 0.5, 1 / n, 1 / n,
+                                    learned.LOG_LO, learned.LOG_HI)
+    rm = rm.cpu().numpy()
+    inside = (y >= learned.LOG_LO) & (y <= learned.LOG_HI)
+    assert fb == np.count_nonzero(~inside)
+    np.testing.assert_allclose(rm[inside], rstar * np.exp(y[inside]), rtol=1e-12)
+    assert np.all(rm[~inside] == rstar)
+    # non-finite parameters: every source falls back to the fixed rule
+    bad = p.copy()
+    bad[mlp.B3] = np.nan
+    rm, fb = fora.fora_predict_rmax(Grmat, _dev(srcs, torch.int32), fora.fora_mlp_to_bf16(_dev(bad)),
+                                    0.2, 0.5, 1 / n, 1 / n, learned.LOG_LO, learned.LOG_HI)
+    assert fb == len(srcs) and np.all(rm.cpu().numpy() == rstar)
+    # outputs far outside the trained range fall back too
+    big = p.copy()
+    big[mlp.B3] = 50.0
+    rm, fb = fora.fora_predict_rmax(Grmat, _dev(srcs, torch.int32), fora.fora_mlp_to_bf16(_dev(big)),
+                                    0.2, 0.5, 1 / n, 1 / n, learned.LOG_LO, learned.LOG_HI)
+    assert fb == len(srcs)
+
+
+def test_push_sweep_matches_reference_sweep():
+    g = synth.uniform_out_graph(1000, 10, seed=1)
+    G = fora.Graph.from_numpy(g.rowptr, g.colidx)
+    srcs = [0, 17, 999]
+    qs = fora.make_queries(srcs, k=1, n=g.n, delta=1e-3, pf=1e-3)
+    E, W = fora.fora_push_sweep(G, qs, learned.MULTS)
+    c = oracle.constants(g.m, 0.2, 0.5, 1e-3, 1e-3)
+    exact_cases = 0
+    for i, s in enumerate(srcs):
+        ref = oracle.push_sweep(g, s, 0.2, c["rmax"] * learned.MULTS, c["omega_unit"])
+        assert np.all(np.diff(E[i]) >= 0)
+        # FP32 residues on the device: where no residue sits within 1e-5 of its
+        # threshold the same nodes are pushed in every round and E is exact
+        if ref["min_margin"] > 1e-5:
+            exact_cases += 1
+            np.testing.assert_array_equal(E[i], ref["E"])
+        else:
+            np.testing.assert_allclose(E[i], ref["E"], rtol=1e-3)
+        # a node's ceil(r omega_unit) can differ by one where r omega_unit is
+        # within FP32 rounding of an integer
+        dW = np.abs(W[i].astype(np.int64) - ref["W"])
+        assert np.all(dW <= np.maximum(2, 1e-3 * ref["W"])), (dW, ref["W"])
+    assert exact_cases >= 1
+
+
+def test_training_fits_and_predicts(grmat, Grmat):
+    # a smooth synthetic target of the real features: the GPU-trained model fits it
+    srcs = np.arange(0, 4096, 2)
+    X = learned.features(Grmat, srcs).cpu().numpy()
+    y = 0.5 * np.tanh(X[:, 0] - 2.0) + 0.3 * X[:, 2]
+    model = learned.Model.init(X, seed=1)
+    before = model.mse(X, y)
+    model.train(X, y, epochs=60, lr=3e-3, batch=512)
+    after = model.mse(X, y)
+    assert after < 0.2 * before and after < 0.01
+    rm, fb = model.predict_rmax(Grmat, srcs[:256])
+    assert fb == 0 and np.all(np.isfinite(rm.cpu().numpy()))
+    # the BF16 inference copy predicts what the FP32 model does
+    rstar = oracle.constants(grmat.m, 0.2, 0.5, 1 / grmat.n, 1 / grmat.n)["rmax"]
+    y32 = fora.fora_mlp_forward(_dev(X[:256]), model.params).cpu().numpy()
+    assert np.abs(np.log(rm.cpu().numpy() / rstar) - y32).max() < 0.05
+
+
+@pytest.mark.parametrize("mult", [0.25, 8.0])
+def test_eps_guarantee_on_gpu_at_other_rmax(mult):
+    # Lemma 2 does not depend on r_max: the GPU path keeps the guarantee
+    g = synth.uniform_out_graph(1000, 10, seed=1)
+    G = fora.Graph.from_numpy(g.rowptr, g.colidx)
+    pi = exact.dense_ppr(g, 0.2)[0]
+    c = oracle.constants(g.m, 0.2, 0.5, 1e-3, 1e-3)
+    R = 64
+    qs = fora.make_queries([0] * R, k=10, seed=list(range(R)), n=g.n, rmax=c["rmax"] * mult)
+    ws = fora.workspace(G, R)
+    fora.fora_ssppr_batch(G, qs, ws=ws)
+    est = fora.fora_workspace_views(G, R, ws)["pi_hat"].cpu().numpy().astype(np.float64)
+    mask = pi >= 1e-3
+    fails = (np.abs(est[:, mask] - pi[mask]) > 0.5 * pi[mask]).sum()
+    assert fails <= st.binom(R * mask.sum(), 1e-3).ppf(1 - 1e-6)
+    assert np.abs(est.mean(0) - pi).sum() < 0.02
