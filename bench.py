@@ -73,6 +73,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy, whose HBM counter "
                          "readings calibrate FETCH_SIZE / WRITE_SIZE")
@@ -150,6 +151,39 @@ def main():
                     traffic_source=traffic_src, kernel="k_walks", bytes_per_launch=alg_bytes,
                     avg_launch_ms=round(walk_s * 1e3, 3))
 
+    learned_leg = None
+    model_path = os.path.join(ROOT, "paper_1908_10583_amd", "models",
+                              f"{args.workload}_rmax_mlp.json")
+    if not args.no_learned and os.path.exists(model_path):
+        from paper_1908_10583_amd import learned
+        model = learned.Model.load(model_path)
+        src_t = torch.as_tensor(srcs, dtype=torch.int32, device="cuda:0")
+
+        def learned_step(stats=False):
+            rm, fb = model.predict_rmax(G, src_t, alpha, eps)
+            q_l = fora.make_queries(srcs, alpha=alpha, eps=eps, k=k, seed=seed, n=g.n,
+                                    rmax=rm.cpu().numpy())
+            return fora.fora_ssppr_batch(G, q_l, kmax=k, ws=ws, out=(ids, vals),
+                                         stats=stats), fb
+
+        for _ in range(args.warmup):
+            learned_step()
+        torch.cuda.synchronize()
+        tl = time.perf_counter()
+        l_steps = 0
+        for _ in range(args.steps):
+            res_l, fb = learned_step(stats=True)
+            l_steps += sum(s["steps"] for s in res_l.stats)
+        torch.cuda.synchronize()
+        dtl = time.perf_counter() - tl
+        learned_leg = dict(queries_per_s=round(B * args.steps / dtl, 2),
+                           walk_steps_per_s=l_steps / dtl,
+                           ms_per_step=round(dtl / args.steps * 1e3, 3), fallbacks=fb,
+                           model=os.path.relpath(model_path, ROOT),
+                           note="r_max per source from the BF16 MLP, inference inside the "
+                                "timed step; the eps guarantee holds for any r_max (Lemma 2)")
+        log(f"batched + learned r_max: {B * args.steps / dtl:.1f} q/s")
+
     graph_mode = None
     if graph_rounds > 0:
         G.set_tuning(graph_rounds=graph_rounds)
@@ -200,6 +234,7 @@ def main():
                    "k": k, "batch": B},
         "queries_per_s": round(qps, 2),
         "plain_single_query": single,
+        "batched_learned_rmax": learned_leg,
         "graph_replay": graph_mode,
         "tuning": tuning,
         "phases_ms": {p: round(float(np.mean([stats0[0][p]])), 3)

@@ -86,7 +86,7 @@ typedef struct fora_query {
 typedef struct fora_views {
   float *residue;             /* r(s, v), FP32 [batch][n]                     */
   float *reserve;             /* q(s, v), FP32 [batch][n]                     */
-  uint32_t *walk_count;       /* walks ending at v, [batch][n]                */
+  uint64_t *walk_count;       /* walks ending at v, [batch][n]                */
   uint64_t *walk_weight_fx;   /* sum of walk weights ending at v, unsigned
                                  fixed point with 62 fraction bits [batch][n] */
   float *pi_hat;              /* q + walk weight, FP32 [batch][n]             */
@@ -146,8 +146,8 @@ int fora_workspace_views(const fora_graph *g, int32_t batch, void *d_ws,
  * h_stats (nullable) makes the call wait and fill the counters.
  * Errors: FORA_E_ARG for any parameter outside the ranges of fora_query,
  * FORA_E_NOMEM if ws_bytes < fora_workspace_size(g, 1),
- * FORA_E_OVERFLOW if W >= 2^32 (walk counts are 32-bit) or some
- * omega_v >= 2^32, FORA_E_HIP. */
+ * FORA_E_OVERFLOW if some omega_v >= 2^32 (the walk index j within a node
+ * is a 32-bit Philox counter word), FORA_E_HIP. */
 int fora_ssppr(const fora_graph *g, int32_t src, double alpha, double eps,
                double delta, double pf, int32_t k, double opt_rmax,
                uint64_t seed, void *d_ws, size_t ws_bytes,

@@ -27,6 +27,8 @@ struct fora_graph {
   int32_t* in_colidx_owned = nullptr;
   int32_t* inhub_node_owned = nullptr;
   fora::u64* inhub_base_owned = nullptr;
+  uint32_t* rec_owned = nullptr;
+  uint32_t* rec_q_owned = nullptr;
   int device = 0;
   int cus = 256;
   // pinned host slots for the small read-backs of the push loop
@@ -117,7 +119,7 @@ QueryDev plan_query(const fora_graph* g, const fora_query& q) {
 
 int error_code_from_flags(int flags) {
   if (flags & kErrOmegaOverflow)
-    return fail(FORA_E_OVERFLOW, "walk count overflow (omega_v >= 2^32 or W >= 2^32)");
+    return fail(FORA_E_OVERFLOW, "walk count overflow (some omega_v >= 2^32)");
   if (flags & kErrFrontierOverflow) return fail(FORA_E_OVERFLOW, "frontier overflow");
   if (flags & kErrLogOverflow) return fail(FORA_E_OVERFLOW, "frontier log capacity too small");
   if (flags & kErrTopk) return fail(FORA_E_HIP, "top-k selection inconsistent");
@@ -392,7 +394,7 @@ Layout make_layout(const GraphDev& g, int32_t batch) {
   L.qstats = take(sizeof(StatSlot) * (size_t)kStatSlots * batch);
   L.r = take(4 * cap);
   L.q = take(4 * cap);
-  L.cnt = take(4 * cap);
+  L.cnt = take(8 * cap);
   L.acc = take(8 * cap);
   L.hist = take(4 * (size_t)kHistBins * batch);
   L.cand_cnt = take(4 * (size_t)batch);
@@ -432,7 +434,7 @@ Ws carve(const Layout& L, void* base) {
   w.queries = (QueryDev*)(p + L.queries);
   w.r = (float*)(p + L.r);
   w.q = (float*)(p + L.q);
-  w.cnt = (uint32_t*)(p + L.cnt);
+  w.cnt = (u64*)(p + L.cnt);
   w.acc = (u64*)(p + L.acc);
   w.pi = (float*)(p + L.pi);
   w.fr[0] = (u64*)(p + L.fr0);
@@ -545,6 +547,33 @@ int build_reverse(fora_graph* g, hipStream_t s) {
   return FORA_OK;
 }
 
+// Walk records (one 8-byte header plus one word per out-edge per node).
+int build_records(fora_graph* g, hipStream_t s) {
+  const int64_t n = g->dev.n;
+  const int64_t words = g->dev.m + 3 * n;  // bound on sum of 2 ceil((2 + d) / 2)
+  const int64_t tiles = (n + 2047) / 2048;
+  int32_t* tmp = nullptr;
+  uint32_t* tsum = nullptr;
+  auto release = [&]() {
+    if (tmp) (void)hipFree(tmp);
+    if (tsum) (void)hipFree(tsum);
+  };
+  if (hipMalloc(&g->rec_owned, sizeof(uint32_t) * (size_t)words) != hipSuccess ||
+      hipMalloc(&g->rec_q_owned, sizeof(uint32_t) * ((size_t)n + 1)) != hipSuccess ||
+      hipMalloc(&tmp, sizeof(int32_t) * (size_t)n) != hipSuccess ||
+      hipMalloc(&tsum, sizeof(uint32_t) * (size_t)tiles) != hipSuccess) {
+    release();
+    return fail(FORA_E_NOMEM, "hipMalloc of the walk records failed");
+  }
+  g->dev.rec = g->rec_owned;
+  g->dev.rec_q = g->rec_q_owned;
+  hipError_t e = launch_build_records(g->dev, g->rec_q_owned, g->rec_owned, tmp, tsum, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  release();
+  if (e != hipSuccess) return fail(FORA_E_HIP, std::string("walk records: ") + hipGetErrorString(e));
+  return FORA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -569,6 +598,8 @@ int fora_build_csr(int32_t n, int64_t m, const int32_t* d_rowptr, const int32_t*
     if (g->in_colidx_owned) (void)hipFree(g->in_colidx_owned);
     if (g->inhub_node_owned) (void)hipFree(g->inhub_node_owned);
     if (g->inhub_base_owned) (void)hipFree(g->inhub_base_owned);
+    if (g->rec_owned) (void)hipFree(g->rec_owned);
+    if (g->rec_q_owned) (void)hipFree(g->rec_q_owned);
     if (g->info_owned) (void)hipFree(g->info_owned);
     if (g->flags_owned) (void)hipFree(g->flags_owned);
     if (g->pinned) (void)hipHostFree(g->pinned);
@@ -602,7 +633,8 @@ int fora_build_csr(int32_t n, int64_t m, const int32_t* d_rowptr, const int32_t*
     return cleanup(FORA_E_GRAPH, "a node has out-degree 0 (dangling)");
   g->dev.max_deg = host_flags[1];
   g->dev.n_hubs = host_flags[2];
-  const int rrc = build_reverse(g, s);
+  int rrc = build_reverse(g, s);
+  if (rrc == FORA_OK) rrc = build_records(g, s);
   if (rrc != FORA_OK) {
     const std::string msg = g_err;
     return cleanup(rrc, msg);
@@ -640,6 +672,8 @@ int fora_free_graph(fora_graph* g) {
   if (g->in_colidx_owned) (void)hipFree(g->in_colidx_owned);
   if (g->inhub_node_owned) (void)hipFree(g->inhub_node_owned);
   if (g->inhub_base_owned) (void)hipFree(g->inhub_base_owned);
+  if (g->rec_owned) (void)hipFree(g->rec_owned);
+  if (g->rec_q_owned) (void)hipFree(g->rec_q_owned);
   if (g->info_owned) (void)hipFree(g->info_owned);
   if (g->flags_owned) (void)hipFree(g->flags_owned);
   if (g->pinned) (void)hipHostFree(g->pinned);
@@ -669,7 +703,7 @@ int fora_workspace_views(const fora_graph* g, int32_t batch, void* d_ws, fora_vi
   const Ws w = carve(L, d_ws);
   v->residue = w.r;
   v->reserve = w.q;
-  v->walk_count = w.cnt;
+  v->walk_count = (uint64_t*)w.cnt;
   v->walk_weight_fx = (uint64_t*)w.acc;
   v->pi_hat = w.pi;
   return FORA_OK;

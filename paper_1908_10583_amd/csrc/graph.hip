@@ -186,6 +186,47 @@ hipError_t launch_build_reverse(const GraphDev& g, int32_t* in_rowptr, int32_t* 
   return hipGetLastError();
 }
 
+// Walk records (see GraphDev): record lengths in 8-byte units, their
+// exclusive prefix (the record starts), then one wavefront per node fills a
+// record: lane 0 the header, all lanes the neighbours' record starts.
+__global__ void k_rec_len(const int2* __restrict__ info, int32_t n, int32_t* len) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    len[v] = (2 + info[v].y + 1) / 2;
+}
+
+__global__ void k_fill_rec(const int2* __restrict__ info, const int32_t* __restrict__ colidx,
+                           int32_t n, const uint32_t* __restrict__ rec_q, uint32_t* rec) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t v = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); v < n;
+       v += waves) {
+    const int2 inf = info[v];
+    uint32_t* r = rec + 2 * (size_t)rec_q[v];
+    if (lane == 0) {
+      r[0] = (uint32_t)inf.y;
+      r[1] = (uint32_t)v;
+      if ((inf.y & 1) != 0) r[2 + inf.y] = 0u;  // pad to an even word count
+    }
+    for (int i = lane; i < inf.y; i += 64) r[2 + i] = rec_q[colidx[(int64_t)inf.x + i]];
+  }
+}
+
+hipError_t launch_build_records(const GraphDev& g, uint32_t* rec_q, uint32_t* rec, int32_t* tmp,
+                                uint32_t* tsum, hipStream_t s) {
+  const int64_t n = g.n;
+  const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  const int bn = (int)std::min<int64_t>((n + 255) / 256, 16384);
+  k_rec_len<<<bn, 256, 0, s>>>(g.info, g.n, tmp);
+  k_tile_sum<<<(unsigned)tiles, 256, 0, s>>>(tmp, n, tsum);
+  k_tile_scan<<<1, 1024, 0, s>>>(tsum, tiles);
+  // the starts go to rec_q (rec_q[n] = total units); tmp is reused as scratch
+  k_tile_apply<<<(unsigned)tiles, 256, 0, s>>>(tmp, n, tsum, (int32_t*)rec_q, tmp);
+  const int wb = (int)std::min<int64_t>((n + 3) / 4, 65536);
+  k_fill_rec<<<wb, 256, 0, s>>>(g.info, g.colidx, g.n, rec_q, rec);
+  return hipGetLastError();
+}
+
 hipError_t launch_list_inhubs(const int32_t* in_rowptr, int32_t n, int32_t* list, int32_t* count,
                               int32_t cap, hipStream_t s) {
   const int bn = (int)std::min<int64_t>((n + 255) / 256, 16384);

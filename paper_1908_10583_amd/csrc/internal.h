@@ -5,7 +5,7 @@
 //   qstats    QueryStats[batch]: per-query counters (device side)
 //   queries   QueryDev[batch]: per-query constants computed on the host
 //   r, q      float[batch][n]   residue / reserve (FP32)
-//   cnt       uint32[batch][n]  walk end-point counts
+//   cnt       uint64[batch][n]  walk end-point counts
 //   acc       uint64[batch][n]  walk weights, fixed point (62 fraction bits)
 //   pi        float[batch][n]   q + acc, the estimate
 //   fr0/fr1   uint64[batch*n]   frontier entries (query << 32 | node)
@@ -106,6 +106,11 @@ struct GraphDev {
   const int32_t* inhub_node;
   const u64* inhub_base;      // first piece of each, exclusive prefix
   u64 inhub_pieces;           // total pieces
+  // walk records: node v's record starts at 8-byte unit rec_q[v] and holds
+  // the 32-bit words d(v), v, then rec_q of each out-neighbour in CSR order
+  // (padded to an even word count)
+  const uint32_t* rec;
+  const uint32_t* rec_q;
 };
 
 struct Layout {
@@ -127,7 +132,7 @@ struct Ws {
   QueryDev* queries;
   float* r;
   float* q;
-  uint32_t* cnt;
+  u64* cnt;
   u64* acc;
   float* pi;
   u64* fr[2];
@@ -199,6 +204,8 @@ hipError_t launch_topk(const GraphDev& g, const Ws& w, const Layout& L, int batc
                        int kmax, int32_t* d_ids, float* d_vals, hipStream_t s);
 hipError_t launch_build_reverse(const GraphDev& g, int32_t* in_rowptr, int32_t* in_colidx,
                                 int32_t* cursor, uint32_t* tsum, hipStream_t s);
+hipError_t launch_build_records(const GraphDev& g, uint32_t* rec_q, uint32_t* rec, int32_t* tmp,
+                                uint32_t* tsum, hipStream_t s);
 hipError_t launch_list_inhubs(const int32_t* in_rowptr, int32_t n, int32_t* list, int32_t* count,
                               int32_t cap, hipStream_t s);
 hipError_t launch_seed_frontier(const GraphDev& g, const Ws& w, const Layout& L, int batch, int t,

@@ -100,7 +100,6 @@ __global__ __launch_bounds__(kScanThreads) void k_plan_scan(
     ctrl->walks = carry_w;
     plan_off[carry_e] = carry_w;
     ctrl->chunk_next = 0;
-    if (carry_w >= 4294967296ull) atomicOr(&ctrl->error, kErrOmegaOverflow);
   }
 }
 

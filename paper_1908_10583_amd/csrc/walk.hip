@@ -8,6 +8,11 @@
 // floor(U * d(x) / 2^64) of x, where U = word1 * 2^32 + word2. At its end
 // point t it adds 1 to cnt[t] and its entry's fixed-point weight to acc[t].
 //
+// Moves read the walk records (GraphDev): one step loads the chosen
+// neighbour's record start from the current record and then that
+// neighbour's 8-byte header (degree, id), so a step on a low-degree node
+// touches one new cache line instead of a node-table line and an edge line.
+//
 // Schedule: a persistent grid; each wavefront takes chunks of `chunk`
 // consecutive walk ids from a device work queue and keeps all 64 lanes busy:
 // a lane whose walk ends takes the next id of the chunk at once (ballot +
@@ -46,8 +51,9 @@ __device__ __forceinline__ u64 wave_find_entry(const u64* __restrict__ off, u64 
 __global__ __launch_bounds__(kWalkBlock) void k_walks(
     const u64* __restrict__ plan_gi, const u64* __restrict__ plan_off,
     const u64* __restrict__ plan_wfx, Ctrl* ctrl, const QueryDev* __restrict__ Q,
-    QueryStatsDev* QS, const int2* __restrict__ info, const int32_t* __restrict__ colidx,
-    int n, uint32_t* __restrict__ cnt, u64* __restrict__ acc, int chunk) {
+    QueryStatsDev* QS, const int2* __restrict__ info, const uint32_t* __restrict__ rec,
+    const uint32_t* __restrict__ rec_q, int n, u64* __restrict__ cnt, u64* __restrict__ acc,
+    int chunk) {
   if (ctrl->error || ctrl->skip) return;
   const u64 W = ctrl->walks;
   const u64 E = ctrl->entries;
@@ -59,6 +65,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
   int b = 0;
   uint32_t v = 0, j = 0, step = 0, k0 = 0, k1 = 0, ta = 0;
   int32_t x = 0;
+  uint32_t q = 0, deg = 1;  // record start and out-degree of x
   u64 wfx = 0;
   int stat_b = -1;
   u64 stat_steps = 0;
@@ -108,6 +115,8 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
           v = (uint32_t)gi;
           j = (uint32_t)(id - o_lo);
           x = (int32_t)v;
+          deg = (uint32_t)info[v].y;
+          q = rec_q[v];
           step = 0;
           k0 = Q[b].key0;
           k1 = Q[b].key1;
@@ -137,7 +146,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
       const uint4 y = philox4x32_10(make_uint4(v, j, step, 0u), k0, k1);
       if (y.x < ta) {
         const size_t t = (size_t)b * n + x;
-        atomicAdd(&cnt[t], 1u);
+        atomicAdd(&cnt[t], 1ull);
         atomicAdd(&acc[t], wfx);
         if (b != stat_b) {
           if (stat_b >= 0) atomicAdd(&QS[(size_t)stat_b * kStatSlots + slot].steps, stat_steps);
@@ -147,9 +156,13 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
         stat_steps += step;
         active = false;
       } else {
-        const int2 inf = info[x];
-        const uint32_t idx = mul_shift_index(y.y, y.z, (uint32_t)inf.y);
-        x = colidx[(int64_t)inf.x + idx];
+        // the chosen neighbour's record start sits in x's record, usually in
+        // the line its header came from; then the neighbour's header
+        const uint32_t idx = mul_shift_index(y.y, y.z, deg);
+        q = rec[2 * (size_t)q + 2 + idx];
+        const uint2 h = reinterpret_cast<const uint2*>(rec)[q];
+        deg = h.x;
+        x = (int32_t)h.y;
         ++step;
       }
     }
@@ -165,7 +178,8 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
 
 hipError_t launch_walks(const GraphDev& g, const Ws& w, int blocks, int chunk, hipStream_t s) {
   k_walks<<<blocks, kWalkBlock, 0, s>>>(w.plan_gi, w.plan_off, w.plan_wfx, w.ctrl, w.queries,
-                                        w.qstats, g.info, g.colidx, g.n, w.cnt, w.acc, chunk);
+                                        w.qstats, g.info, g.rec, g.rec_q, g.n, w.cnt, w.acc,
+                                        chunk);
   return hipGetLastError();
 }
 

@@ -223,7 +223,7 @@ def fora_workspace_views(g: Graph, batch: int, ws: torch.Tensor) -> dict:
 
     return dict(residue=view(v.residue, torch.float32, 4),
                 reserve=view(v.reserve, torch.float32, 4),
-                walk_count=view(v.walk_count, torch.int32, 4),        # uint32 bits
+                walk_count=view(v.walk_count, torch.int64, 8),        # uint64 bits
                 walk_weight_fx=view(v.walk_weight_fx, torch.int64, 8),  # uint64 bits
                 pi_hat=view(v.pi_hat, torch.float32, 4))
 

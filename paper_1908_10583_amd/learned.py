@@ -35,7 +35,7 @@ def features(G, srcs, alpha=0.2, eps=0.5, delta=None, pf=None):
                               alpha, eps, delta, pf)
 
 
-def sweep(G, srcs, alpha=0.2, eps=0.5, delta=None, pf=None, batch=64, log=None):
+def sweep(G, srcs, alpha=0.2, eps=0.5, delta=None, pf=None, batch=128, log=None):
     """Push work E[s, i] and walk counts W[s, i] at every threshold of MULTS."""
     srcs = np.asarray(srcs)
     E = np.zeros((len(srcs), len(MULTS)), np.int64)
@@ -48,7 +48,7 @@ def sweep(G, srcs, alpha=0.2, eps=0.5, delta=None, pf=None, batch=64, log=None):
         e, w = fora.fora_push_sweep(G, qs, MULTS, ws=ws)
         E[i:i + len(part)] = e
         W[i:i + len(part)] = w
-        if log and (i // batch) % 20 == 0:
+        if log and (i // batch) % 8 == 0:
             log(f"sweep {i + len(part)}/{len(srcs)} ({time.perf_counter() - t0:.1f}s)")
     return E, W
 
@@ -76,17 +76,38 @@ def calibrate(G, srcs, alpha=0.2, eps=0.5, mults=(0.25, 1.0, 8.0), batch=64):
 
 
 def labels(E, W, cost):
+    """Per-source label ln(mult) at the modelled cost minimum: the grid's
+    argmin refined by the vertex of the parabola through it and its two grid
+    neighbours (the grid is uniform in ln mult), kept within the grid."""
     total = cost["ms_per_edge_op"] * E.astype(np.float64) + \
         cost["ms_per_walk"] * W.astype(np.float64)
+    x = np.log(MULTS)
+    h = x[1] - x[0]
     best = np.argmin(total, axis=1)
-    return np.log(MULTS[best]), total
+    y = x[best].copy()
+    inner = (best > 0) & (best < len(MULTS) - 1)
+    rows = np.flatnonzero(inner)
+    cm = total[rows, best[rows] - 1]
+    c0 = total[rows, best[rows]]
+    cp = total[rows, best[rows] + 1]
+    curv = cm - 2.0 * c0 + cp
+    ok = curv > 0
+    off = np.zeros(rows.size)
+    off[ok] = 0.5 * (cm[ok] - cp[ok]) / curv[ok]
+    y[rows] += np.clip(off, -0.5, 0.5) * h
+    return y, total
 
 
 class Model:
     """MLP parameters on the device (FP32 master copy, BF16 inference copy)."""
 
-    def __init__(self, params: torch.Tensor):
+    def __init__(self, params: torch.Tensor, trained_on=((0.2, 0.5),)):
         self.params = params
+        # the (alpha, eps) pairs of the training set; other queries keep eqn:rmax
+        self.trained_on = [tuple(map(float, x)) for x in trained_on]
+
+    def covers(self, alpha: float, eps: float) -> bool:
+        return any(abs(alpha - a) < 1e-12 and abs(eps - e) < 1e-12 for a, e in self.trained_on)
 
     @classmethod
     def init(cls, X: np.ndarray, seed=0, device="cuda"):
@@ -108,6 +129,7 @@ class Model:
         return cls(torch.from_numpy(p).to(device))
 
     def train(self, X, y, epochs=300, lr=3e-3, batch=1024, seed=0, log=None):
+        self._pb = None
         dev = self.params.device
         Xt = torch.as_tensor(np.asarray(X, np.float32), device=dev)
         yt = torch.as_tensor(np.asarray(y, np.float32), device=dev)
@@ -145,23 +167,30 @@ class Model:
         return float(np.mean((yp - np.asarray(y)) ** 2))
 
     def bf16(self):
-        return fora.fora_mlp_to_bf16(self.params)
+        """The BF16 inference copy (made once per set of trained weights)."""
+        if getattr(self, "_pb", None) is None:
+            self._pb = fora.fora_mlp_to_bf16(self.params)
+        return self._pb
 
     def predict_rmax(self, G, srcs, alpha=0.2, eps=0.5, delta=None, pf=None):
         delta = 1.0 / G.n if delta is None else delta
         pf = 1.0 / G.n if pf is None else pf
-        return fora.fora_predict_rmax(G, torch.as_tensor(np.asarray(srcs), dtype=torch.int32),
-                                      self.bf16(), alpha, eps, delta, pf, LOG_LO, LOG_HI)
+        if not torch.is_tensor(srcs):
+            srcs = torch.as_tensor(np.asarray(srcs), dtype=torch.int32)
+        return fora.fora_predict_rmax(G, srcs, self.bf16(), alpha, eps, delta, pf,
+                                      LOG_LO, LOG_HI)
 
     def save(self, path):
         with open(path, "w") as f:
-            json.dump(dict(params=self.params.cpu().numpy().tolist()), f)
+            json.dump(dict(params=self.params.cpu().numpy().tolist(),
+                           trained_on=self.trained_on), f)
 
     @classmethod
     def load(cls, path, device="cuda"):
         with open(path) as f:
-            p = np.asarray(json.load(f)["params"], np.float32)
-        return cls(torch.from_numpy(p).to(device))
+            d = json.load(f)
+        p = np.asarray(d["params"], np.float32)
+        return cls(torch.from_numpy(p).to(device), d.get("trained_on", ((0.2, 0.5),)))
 
 
 def time_queries(G, srcs, rmax=None, alpha=0.2, eps=0.5, k=500):
@@ -200,8 +229,14 @@ def time_batched(G, srcs, rmax=None, alpha=0.2, eps=0.5, k=500, batch=128):
 
 def main(argv=None):
     """Train on a workload's training sources and evaluate on its held-out
-    sources against the fixed eqn:rmax rule; prints one JSON report."""
+    sources against the fixed eqn:rmax rule; prints one JSON report.
+
+    The cost sweep can run in pieces: ``--sweep-range a:b --sweep-dir D``
+    sweeps training sources a..b-1 (plus the unit-cost calibration when
+    a = 0) into D; a later call with ``--sweep-dir D`` and no range trains
+    and evaluates from what D holds, sweeping whatever is missing."""
     import argparse
+    import os
     import sys
 
     import synth
@@ -211,6 +246,10 @@ def main(argv=None):
     ap.add_argument("--heldout", type=int, default=2048)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--timed", type=int, default=512, help="held-out sources timed one by one")
+    ap.add_argument("--sweep-batch", type=int, default=128)
+    ap.add_argument("--sweep-dir", default=None)
+    ap.add_argument("--sweep-range", default=None, help="a:b, sweep only these training sources")
+    ap.add_argument("--model-out", default=None)
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -219,19 +258,66 @@ def main(argv=None):
     g, srcs = synth.workload(args.workload)
     G = fora.Graph.from_numpy(g.rowptr, g.colidx)
     tr, ho = srcs[:args.train], srcs[-args.heldout:]
+    assert len(srcs) >= args.train + args.heldout, "training and held-out sources overlap"
     log(f"graph {g.name} n={g.n} m={g.m}; train {len(tr)} held-out {len(ho)}")
-    t0 = time.perf_counter()
-    cost = calibrate(G, tr)
+    sd = args.sweep_dir
+    if sd:
+        os.makedirs(sd, exist_ok=True)
+
+    def piece_path(a, b):
+        return os.path.join(sd, f"{args.workload}_sweep_{a}_{b}.npz")
+
+    def run_piece(a, b):
+        t0 = time.perf_counter()
+        E, W = sweep(G, tr[a:b], batch=args.sweep_batch, log=log)
+        log(f"swept {a}:{b} in {time.perf_counter() - t0:.1f}s")
+        if sd:
+            np.savez(piece_path(a, b), E=E, W=W, srcs=tr[a:b])
+        return E, W
+
+    cost_path = os.path.join(sd, f"{args.workload}_unit_costs.json") if sd else None
+    if cost_path and os.path.exists(cost_path):
+        cost = json.load(open(cost_path))
+    else:
+        cost = calibrate(G, tr)
+        if cost_path:
+            json.dump(cost, open(cost_path, "w"))
     log(f"unit costs {cost}")
-    E, W = sweep(G, tr, log=log)
-    t_sweep = time.perf_counter() - t0
+    if args.sweep_range:
+        # saved in pieces of 1024 sources, so that a cut-off run keeps its work
+        a, b = (int(x) for x in args.sweep_range.split(":"))
+        b = min(b, len(tr))
+        for lo in range(a, b, 1024):
+            run_piece(lo, min(lo + 1024, b))
+        return None
+
+    # assemble the training sweep from saved pieces, sweeping the gaps
+    E = np.zeros((len(tr), len(MULTS)), np.int64)
+    W = np.zeros((len(tr), len(MULTS)), np.uint64)
+    have = np.zeros(len(tr), bool)
+    t_sweep0 = time.perf_counter()
+    if sd:
+        for f in sorted(os.listdir(sd)):
+            if f.startswith(f"{args.workload}_sweep_") and f.endswith(".npz"):
+                a, b = (int(x) for x in f[:-4].split("_")[-2:])
+                z = np.load(os.path.join(sd, f), allow_pickle=False)
+                if b <= len(tr) and np.array_equal(z["srcs"], tr[a:b]):
+                    E[a:b], W[a:b], have[a:b] = z["E"], z["W"], True
+    for a in range(0, len(tr), 1024):
+        b = min(a + 1024, len(tr))
+        if not have[a:b].all():
+            E[a:b], W[a:b] = run_piece(a, b)
+    t_sweep = time.perf_counter() - t_sweep0
     y, _ = labels(E, W, cost)
     X = features(G, tr).cpu().numpy()
     model = Model.init(X, seed=0)
     t1 = time.perf_counter()
     model.train(X, y, epochs=args.epochs, log=log)
+    torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
-    Eh, Wh = sweep(G, ho)
+    if args.model_out:
+        model.save(args.model_out)
+    Eh, Wh = sweep(G, ho, batch=args.sweep_batch)
     yh, cost_h = labels(Eh, Wh, cost)
     Xh = features(G, ho).cpu().numpy()
     rmax_l, fallbacks = model.predict_rmax(G, ho)
@@ -242,30 +328,43 @@ def main(argv=None):
     i_star = np.abs(np.log(MULTS)).argmin()
     mod_learned = cost_h[np.arange(len(ho)), pick]
     mod_fixed = cost_h[:, i_star]
+    # the best single multiplier for all sources (what a global retuning of
+    # eqn:rmax would reach, with no per-source model)
+    i_glob = int(np.argmin(cost_h.sum(0)))
     timed = ho[:args.timed]
+    log("timing single queries")
     t_fixed = time_queries(G, timed)
     t_learn = time_queries(G, timed, rmax=rmax_l[:args.timed])
+    t_glob = time_queries(G, timed, rmax=np.full(len(timed), rstar * MULTS[i_glob]))
+    log("timing batched queries")
     qps_fixed = time_batched(G, ho)
     qps_learn = time_batched(G, ho, rmax=rmax_l)
     t_inf0 = time.perf_counter()
     model.predict_rmax(G, ho)
     torch.cuda.synchronize()
     t_inf = time.perf_counter() - t_inf0
+
+    def summary(t):
+        return dict(mean=float(t.mean()), p50=float(np.percentile(t, 50)),
+                    p95=float(np.percentile(t, 95)))
+
     rep = dict(workload=args.workload, n=g.n, m=g.m, train=len(tr), heldout=len(ho),
                grid=MULTS.tolist(), unit_costs=cost,
                label_mult_histogram=np.bincount(np.argmin(np.abs(y[:, None] - np.log(MULTS)), 1),
                                                 minlength=len(MULTS)).tolist(),
+               label_std=float(y.std()),
                train_mse=model.mse(X, y), heldout_mse=model.mse(Xh, yh),
                heldout_mse_fixed_rule=float(np.mean(yh ** 2)),
+               heldout_mse_best_constant=float(np.mean((yh - y.mean()) ** 2)),
                fallbacks=fallbacks,
                modelled_cost_ms=dict(fixed_mean=float(mod_fixed.mean()),
                                      learned_mean=float(mod_learned.mean()),
-                                     oracle_best_mean=float(cost_h.min(1).mean())),
-               measured_single_query_ms=dict(
-                   sources=int(len(timed)),
-                   fixed_mean=float(t_fixed.mean()), fixed_p95=float(np.percentile(t_fixed, 95)),
-                   learned_mean=float(t_learn.mean()),
-                   learned_p95=float(np.percentile(t_learn, 95))),
+                                     best_global_mult=float(MULTS[i_glob]),
+                                     best_global_mean=float(cost_h[:, i_glob].mean()),
+                                     per_source_best_mean=float(cost_h.min(1).mean())),
+               measured_single_query_ms=dict(sources=int(len(timed)), fixed=summary(t_fixed),
+                                             learned=summary(t_learn),
+                                             best_global_mult=summary(t_glob)),
                batched_queries_per_s=dict(fixed=qps_fixed, learned=qps_learn),
                sweep_seconds=t_sweep, train_seconds=t_train,
                inference_us_per_source=t_inf / len(ho) * 1e6)

@@ -125,13 +125,73 @@ def _rmat_samples(scale: int, count: int, a: float, b: float, c: float,
     return src.astype(np.int64), dst.astype(np.int64)
 
 
+_RMAT_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "rmat.c")
+_RMAT_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librmat.so")
+_rmat_lib = None
+
+
+def build_sampler(force: bool = False) -> str:
+    """Compile the multithreaded R-MAT sampler (gcc, OpenMP)."""
+    if force or not os.path.exists(_RMAT_LIB) or \
+            os.path.getmtime(_RMAT_LIB) < os.path.getmtime(_RMAT_SRC):
+        import subprocess
+        tmp = _RMAT_LIB + f".tmp{os.getpid()}"
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _RMAT_SRC],
+                       check=True)
+        os.replace(tmp, _RMAT_LIB)
+    return _RMAT_LIB
+
+
+def _load_sampler():
+    global _rmat_lib
+    if _rmat_lib is None:
+        import ctypes
+        lib = ctypes.CDLL(build_sampler())
+        P = ctypes.c_void_p
+        lib.synth_rmat.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                   P, P, P, ctypes.c_int64, P]
+        lib.synth_rmat.restype = ctypes.c_int
+        _rmat_lib = lib
+    return _rmat_lib
+
+
+def _rmat_graph_c(scale, samples, a, b, c, seed):
+    import ctypes
+    n = 1 << scale
+    rowptr = np.empty(n + 1, np.int32)
+    deg0 = np.empty(n, np.int32)
+    cap = samples + n
+    col = np.empty(cap, np.int32)
+    m = np.zeros(1, np.int64)
+    rc = _load_sampler().synth_rmat(scale, samples, a, b, c, seed & (2**64 - 1),
+                                    rowptr.ctypes.data, deg0.ctypes.data, col.ctypes.data,
+                                    cap, m.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"R-MAT sampler failed ({rc})")
+    return rowptr, col[:int(m[0])], deg0
+
+
 def rmat_graph(scale: int, edge_factor: int = 16, a: float = 0.57,
                b: float = 0.19, c: float = 0.19, seed: int = 0,
-               chunk: int = 1 << 24, cache: bool = True) -> Graph:
-    """R-MAT graph on n = 2^scale nodes from ``edge_factor * n`` samples."""
+               chunk: int = 1 << 24, cache: bool = True,
+               sampler: str | None = None) -> Graph:
+    """R-MAT graph on n = 2^scale nodes from ``edge_factor * n`` samples.
+
+    Two samplers draw from the same model with different random streams:
+    ``"numpy"`` (PCG64, level by level; the default up to scale 23) and
+    ``"c"`` (SplitMix64 at counters, multithreaded; the default from scale 24,
+    where numpy takes minutes)."""
     n = 1 << scale
     samples = edge_factor * n
+    sampler = sampler or ("numpy" if scale <= 23 else "c")
     tag = f"rmat-s{scale}-ef{edge_factor}-a{a}-b{b}-c{c}-seed{seed}"
+    if sampler == "c":
+        tag += "-c"
+        rowptr, colidx, deg0 = _rmat_graph_c(scale, samples, a, b, c, seed)
+        return Graph(rowptr, colidx, name=tag, deg_before_fixup=deg0,
+                     params=dict(kind="rmat", scale=scale, edge_factor=edge_factor,
+                                 a=a, b=b, c=c, seed=seed, sampler="c"))
     path = os.path.join(_cache_dir(), tag + ".npz") if cache else None
     if path and os.path.exists(path):
         z = np.load(path, allow_pickle=False)
@@ -209,6 +269,23 @@ def random_walk_plan(g: Graph, entries: int, max_walks: int, seed: int):
     return v, omega, w
 
 
+def poisson_requests(count: int, qps: float, sources: np.ndarray, seed: int,
+                     eps_choices=(0.1, 0.5), k_choices=(50, 500)):
+    """A seeded request trace: arrival times of a Poisson process of rate
+    ``qps`` (exponential gaps), a source drawn uniformly from ``sources``, and
+    eps and k each drawn uniformly from their choices. Returns a list of dicts
+    (id, t, src, eps, k, seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gaps = rng.exponential(1.0 / qps, size=count)
+    t = np.cumsum(gaps) - gaps[0]
+    src = rng.choice(np.asarray(sources), size=count, replace=True)
+    eps = rng.choice(np.asarray(eps_choices, np.float64), size=count)
+    k = rng.choice(np.asarray(k_choices, np.int64), size=count)
+    seeds = rng.integers(0, 2**31, size=count)
+    return [dict(id=i, t=float(t[i]), src=int(src[i]), eps=float(eps[i]), k=int(k[i]),
+                 seed=int(seeds[i])) for i in range(count)]
+
+
 def workload(name: str) -> tuple[Graph, np.ndarray]:
     """The named workloads: graph and source list."""
     if name == "uniform1k":
@@ -217,10 +294,20 @@ def workload(name: str) -> tuple[Graph, np.ndarray]:
     if name == "rmat20":
         g = rmat_graph(20, seed=20)
         return g, sources_uniform(g, 100, seed=2020)
+    if name == "rmat20L":
+        # training sources for a learned r_max on the rmat20 graph, then the
+        # 100 rmat20 sources (held out: disjoint from the training ones)
+        g = rmat_graph(20, seed=20)
+        bench = sources_uniform(g, 100, seed=2020)
+        train = sources_uniform(g, 4096, seed=2021, exclude=bench)
+        return g, np.concatenate([train, bench])
     if name == "rmat23":
         g = rmat_graph(23, seed=23)
         return g, sources_by_degree(g, 1024, seed=2323)
     if name == "rmat22":
         g = rmat_graph(22, seed=22)
         return g, sources_uniform(g, 22048, seed=2222)
+    if name == "rmat26":
+        g = rmat_graph(26, seed=26)
+        return g, sources_uniform(g, 4096, seed=2626)
     raise KeyError(name)

@@ -52,7 +52,7 @@ def _same_query(a, b, i, j, omega_unit):
     assert np.all(close(a["residue"][i], b["residue"][j]))
     om_a = walkcmp.omega(a["residue"][i], omega_unit)
     om_b = walkcmp.omega(b["residue"][j], omega_unit)
-    walkcmp.check(a["walk_count"][i].view(np.uint32), b["walk_count"][j].view(np.uint32),
+    walkcmp.check(a["walk_count"][i].view(np.uint64), b["walk_count"][j].view(np.uint64),
                   om_a, om_b, a["pi_hat"][i], b["pi_hat"][j], w_max=1.0 / omega_unit)
 
 
@@ -81,7 +81,7 @@ def test_results_do_not_depend_on_tuning(g1k, G1k, shape):
     om = walkcmp.omega(v["residue"][0], res.stats["omega_unit"])
     om_ref = np.zeros(g1k.n)
     om_ref[ref["plan"][0]] = ref["plan"][1]
-    if walkcmp.check(v["walk_count"][0].view(np.uint32), ref["cnt"], om, om_ref) == 0:
+    if walkcmp.check(v["walk_count"][0].view(np.uint64), ref["cnt"], om, om_ref) == 0:
         assert res.stats["steps"] == ref["steps"]
 
 

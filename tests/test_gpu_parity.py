@@ -55,8 +55,9 @@ def Grmat12(grmat12):
     return fora.Graph.from_numpy(grmat12.rowptr, grmat12.colidx)
 
 
-def _u32(t):
-    return t.cpu().numpy().view(np.uint32)
+def _cnt(t):
+    """Walk end-point counts (uint64 bits in an int64 tensor) as numpy."""
+    return t.cpu().numpy().view(np.uint64)
 
 
 def _u64(t):
@@ -110,6 +111,19 @@ def test_argument_checks(G1k):
     with pytest.raises(fora.FORAError) as ei:
         fora.fora_ssppr(G1k, 0, k=50, ws=small)
     assert ei.value.code == fora.FORA_E_NOMEM
+
+
+def test_walk_index_overflow_is_an_error(G1k):
+    # one push of the source leaves 0.08 on each of 10 neighbours; with
+    # omega_unit ~ 7e10 each omega_v = ceil(0.08 omega_unit) >= 2^32 does not
+    # fit the 32-bit walk index: the plan is rejected before any walk runs
+    c = oracle.constants(10000, ALPHA, 0.5, 1e-9, 1e-3)
+    assert 0.08 * c["omega_unit"] >= 2**32
+    with pytest.raises(fora.FORAError) as ei:
+        fora.fora_ssppr(G1k, 0, ALPHA, 0.5, 1e-9, 1e-3, 10, rmax=0.05)
+    assert ei.value.code == fora.FORA_E_OVERFLOW
+    # the library stays usable
+    fora.fora_ssppr(G1k, 0, k=10)
 
 
 # ------------------------------------------------------------------ push
@@ -206,7 +220,7 @@ def _walk_compare(g, G, pv, po, pw, key0, key1):
     t_alpha = oracle.constants(g.m, ALPHA, 0.5, 0.01, 0.01)["t_alpha"]
     ref = oracle.walks(g, key0, key1, t_alpha, pv, po, pw)
     got = fora.fora_walk_only(G, pv, po, pw, key0, key1, ALPHA)
-    cnt = _u32(got["cnt"]).astype(np.uint64)
+    cnt = _cnt(got["cnt"])
     assert np.array_equal(cnt, ref["cnt"])
     assert got["steps"] == ref["steps"]
     acc = _u64(got["acc_fx"]).astype(np.float64) / 2.0**62
@@ -234,7 +248,7 @@ def test_walk_only_empty_plan(G1k):
     got = fora.fora_walk_only(G1k, np.zeros(0, np.int32), np.zeros(0, np.uint64),
                               np.zeros(0), 0, 0, ALPHA)
     assert got["steps"] == 0
-    assert int(_u32(got["cnt"]).sum()) == 0
+    assert int(_cnt(got["cnt"]).sum()) == 0
 
 
 # ------------------------------------------------------------------ end to end
@@ -262,7 +276,7 @@ def test_end_to_end_uniform(g1k, G1k, seed):
     om_ref = np.zeros(g1k.n)
     om_ref[ref["plan"][0]] = ref["plan"][1]
     pi = v["pi_hat"][0].cpu().numpy()
-    d_om = walkcmp.check(_u32(v["walk_count"][0]), ref["cnt"], om_gpu, om_ref, pi, ref["pi"],
+    d_om = walkcmp.check(_cnt(v["walk_count"][0]), ref["cnt"], om_gpu, om_ref, pi, ref["pi"],
                          w_max=1.0 / st["omega_unit"])
     if d_om == 0:
         assert st["walks"] == ref["walks"] and st["steps"] == ref["steps"]
@@ -285,7 +299,7 @@ def test_end_to_end_monte_carlo_case(g1k, G1k):
     assert res.stats["rounds"] == 0 and ref["rounds"] == 0
     assert res.stats["walks"] == ref["walks"] == math.ceil(ref["consts"]["omega_unit"])
     assert res.stats["steps"] == ref["steps"]
-    assert np.array_equal(_u32(v["walk_count"][0]).astype(np.uint64), ref["cnt"])
+    assert np.array_equal(_cnt(v["walk_count"][0]), ref["cnt"])
 
 
 @pytest.mark.parametrize("k", [1, 7, 500, 1000])
@@ -328,11 +342,11 @@ def test_batch_matches_single(g1k, G1k):
         om = walkcmp.omega(vb["residue"][i].cpu().numpy(), st["omega_unit"])
         om_ref = np.zeros(g1k.n)
         om_ref[ref["plan"][0]] = ref["plan"][1]
-        walkcmp.check(_u32(vb["walk_count"][i]), ref["cnt"], om, om_ref, pi, ref["pi"],
+        walkcmp.check(_cnt(vb["walk_count"][i]), ref["cnt"], om, om_ref, pi, ref["pi"],
                       w_max=1.0 / st["omega_unit"])
         order = np.lexsort((np.arange(g1k.n), -pi))[:50]
         assert np.array_equal(out.ids[i].cpu().numpy(), order)
     # duplicates (same source and seed) walk identically wherever their plans agree
     om1 = walkcmp.omega(vb["residue"][1].cpu().numpy(), out.stats[1]["omega_unit"])
     om2 = walkcmp.omega(vb["residue"][2].cpu().numpy(), out.stats[2]["omega_unit"])
-    walkcmp.check(_u32(vb["walk_count"][1]), _u32(vb["walk_count"][2]), om1, om2)
+    walkcmp.check(_cnt(vb["walk_count"][1]), _cnt(vb["walk_count"][2]), om1, om2)
