@@ -25,10 +25,10 @@ if ROOT not in sys.path:
 
 METRIC = "walk-steps/s + SSPPR queries/s (eps=0.5, top-500) vs plain FORA, same GPU"
 PEAK_HBM_GBS = 8000.0
-# algorithmic bytes: per walk move 8 B node record + 4 B target id; per walk
-# 8 B plan read (amortised) + 4 B count + 8 B weight at the end point
+# algorithmic bytes: per walk move 8 B node header + 4 B neighbour word; per
+# walk 8 B plan read (amortised) + 8 B count + 8 B weight at the end point
 BYTES_PER_STEP = 12
-BYTES_PER_WALK = 20
+BYTES_PER_WALK = 24
 
 
 def log(msg):
