@@ -74,6 +74,10 @@ def main():
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--max-batch", type=int, default=0,
+                    help="queries per batched call (0: all sources in one call)")
+    ap.add_argument("--single-sample", type=int, default=0,
+                    help="sources timed by the plain single-query loop (0: all)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy, whose HBM counter "
                          "readings calibrate FETCH_SIZE / WRITE_SIZE")
@@ -92,11 +96,26 @@ def main():
     log(f"graph {g.name}: n={g.n} m={g.m} sources={len(srcs)} ({time.perf_counter()-t0:.1f}s)")
     G = fora.Graph.from_numpy(g.rowptr, g.colidx, device="cuda:0")
     B = len(srcs)
-    qs = fora.make_queries(srcs, alpha=alpha, eps=eps, k=k, seed=seed, n=g.n)
-    ws = fora.workspace(G, B)
+    # the sources run in waves of at most --max-batch queries (per-query
+    # state is dense, so large graphs take several waves)
+    WB = min(B, args.max_batch) if args.max_batch else B
+    waves = [(a, min(a + WB, B)) for a in range(0, B, WB)]
+    qs_w = [fora.make_queries(srcs[a:b], alpha=alpha, eps=eps, k=k, seed=seed, n=g.n)
+            for a, b in waves]
+    ws = fora.workspace(G, WB)
     ids = torch.empty((B, k), dtype=torch.int32, device="cuda:0")
     vals = torch.empty((B, k), dtype=torch.float32, device="cuda:0")
-    log(f"workspace {ws.numel()/2**30:.2f} GiB for batch {B}")
+    log(f"workspace {ws.numel()/2**30:.2f} GiB for waves of {WB} ({len(waves)} waves)")
+
+    def run_all(stats=False, queries=None):
+        out = []
+        for i, (a, b) in enumerate(waves):
+            q = qs_w[i] if queries is None else queries[i]
+            res = fora.fora_ssppr_batch(G, q, kmax=k, ws=ws, out=(ids[a:b], vals[a:b]),
+                                        stats=stats)
+            if stats:
+                out.append(res.stats)
+        return out
 
     if args.calib_copy:
         src_t = torch.ones(2**30 // 4, dtype=torch.float32, device="cuda:0")
@@ -109,14 +128,15 @@ def main():
 
     tuning = None
     if not args.no_autotune:
-        sample = fora.make_queries(srcs[:32], alpha=alpha, eps=eps, k=k, seed=seed, n=g.n)
+        sample = fora.make_queries(srcs[:min(32, WB)], alpha=alpha, eps=eps, k=k, seed=seed,
+                                   n=g.n)
         rec = autotune.autotune(G, sample, log=log)
         tuning = dict(rec["tuning"])
     graph_rounds = G.get_tuning()["graph_rounds"]
     G.set_tuning(graph_rounds=0)  # timed region: host-driven rounds, per-phase events
 
     for i in range(args.warmup):
-        fora.fora_ssppr_batch(G, qs, kmax=k, ws=ws, out=(ids, vals))
+        run_all()
         log(f"warmup {i+1}/{args.warmup} done")
     torch.cuda.synchronize()
     step_times, walk_ms, stats0 = [], [], None
@@ -124,24 +144,26 @@ def main():
     t_all = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
-        res = fora.fora_ssppr_batch(G, qs, kmax=k, ws=ws, out=(ids, vals), stats=True)
+        per_wave = run_all(stats=True)
         torch.cuda.synchronize()
         step_times.append(time.perf_counter() - ts)
-        st = res.stats
+        st = [x for w in per_wave for x in w]
         stats0 = st
         total_steps += sum(s["steps"] for s in st)
         total_walks += sum(s["walks"] for s in st)
-        walk_ms.append(st[0]["ms_walk"])
+        ph = {p: sum(w[0][p] for w in per_wave) for p in ("ms_push", "ms_plan", "ms_walk",
+                                                           "ms_topk")}
+        walk_ms.append(ph["ms_walk"] / len(waves))
         log(f"step {i+1}/{args.steps}: {step_times[-1]*1e3:.1f} ms "
-            f"(push {st[0]['ms_push']:.1f} plan {st[0]['ms_plan']:.1f} "
-            f"walk {st[0]['ms_walk']:.1f} topk {st[0]['ms_topk']:.1f})")
+            f"(push {ph['ms_push']:.1f} plan {ph['ms_plan']:.1f} "
+            f"walk {ph['ms_walk']:.1f} topk {ph['ms_topk']:.1f})")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_all
     steps_per_s = total_steps / elapsed
     qps = B * args.steps / elapsed
 
-    per_launch_steps = total_steps / args.steps
-    per_launch_walks = total_walks / args.steps
+    per_launch_steps = total_steps / args.steps / len(waves)
+    per_launch_walks = total_walks / args.steps / len(waves)
     walk_s = float(np.mean(walk_ms)) / 1e3
     alg_bytes = BYTES_PER_STEP * per_launch_steps + BYTES_PER_WALK * per_launch_walks
     achieved = alg_bytes / walk_s / 1e9
@@ -161,10 +183,10 @@ def main():
 
         def learned_step(stats=False):
             rm, fb = model.predict_rmax(G, src_t, alpha, eps)
-            q_l = fora.make_queries(srcs, alpha=alpha, eps=eps, k=k, seed=seed, n=g.n,
-                                    rmax=rm.cpu().numpy())
-            return fora.fora_ssppr_batch(G, q_l, kmax=k, ws=ws, out=(ids, vals),
-                                         stats=stats), fb
+            rm = rm.cpu().numpy()
+            q_l = [fora.make_queries(srcs[a:b], alpha=alpha, eps=eps, k=k, seed=seed, n=g.n,
+                                     rmax=rm[a:b]) for a, b in waves]
+            return run_all(stats=stats, queries=q_l), fb
 
         for _ in range(args.warmup):
             learned_step()
@@ -172,8 +194,8 @@ def main():
         tl = time.perf_counter()
         l_steps = 0
         for _ in range(args.steps):
-            res_l, fb = learned_step(stats=True)
-            l_steps += sum(s["steps"] for s in res_l.stats)
+            per_wave, fb = learned_step(stats=True)
+            l_steps += sum(s["steps"] for w in per_wave for s in w)
         torch.cuda.synchronize()
         dtl = time.perf_counter() - tl
         learned_leg = dict(queries_per_s=round(B * args.steps / dtl, 2),
@@ -187,11 +209,11 @@ def main():
     graph_mode = None
     if graph_rounds > 0:
         G.set_tuning(graph_rounds=graph_rounds)
-        fora.fora_ssppr_batch(G, qs, kmax=k, ws=ws, out=(ids, vals))  # capture
+        run_all()  # capture
         torch.cuda.synchronize()
         tg = time.perf_counter()
         for _ in range(args.steps):
-            fora.fora_ssppr_batch(G, qs, kmax=k, ws=ws, out=(ids, vals))
+            run_all()
         torch.cuda.synchronize()
         dtg = time.perf_counter() - tg
         graph_mode = dict(queries_per_s=round(B * args.steps / dtg, 2),
@@ -206,16 +228,18 @@ def main():
               torch.empty(k, dtype=torch.float32, device="cuda:0"))
         fora.fora_ssppr(G, int(srcs[0]), alpha, eps, k=k, seed=seed, ws=ws1, out=o1)
         torch.cuda.synchronize()
+        sample = srcs[:args.single_sample] if args.single_sample else srcs
         t1 = time.perf_counter()
         s_steps = 0
-        for s in srcs:
+        for s in sample:
             r = fora.fora_ssppr(G, int(s), alpha, eps, k=k, seed=seed, ws=ws1, out=o1, stats=True)
             s_steps += r.stats["steps"]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
-        single = dict(queries_per_s=round(B / dt, 2), walk_steps_per_s=s_steps / dt,
-                      ms_per_query=round(dt / B * 1e3, 3))
-        log(f"plain single-query loop: {B/dt:.1f} q/s")
+        ns = len(sample)
+        single = dict(queries_per_s=round(ns / dt, 2), walk_steps_per_s=s_steps / dt,
+                      ms_per_query=round(dt / ns * 1e3, 3), sources=ns)
+        log(f"plain single-query loop: {ns/dt:.1f} q/s over {ns} sources")
         del ws1
 
     cpu = None
@@ -231,14 +255,13 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{g.name}, {B} sources, batched", "n": g.n, "m": g.m,
                    "sources": B, "alpha": alpha, "eps": eps, "delta": "1/n", "pf": "1/n",
-                   "k": k, "batch": B},
+                   "k": k, "batch": WB, "waves": len(waves)},
         "queries_per_s": round(qps, 2),
         "plain_single_query": single,
         "batched_learned_rmax": learned_leg,
         "graph_replay": graph_mode,
         "tuning": tuning,
-        "phases_ms": {p: round(float(np.mean([stats0[0][p]])), 3)
-                      for p in ("ms_push", "ms_plan", "ms_walk", "ms_topk")},
+        "phases_ms": {p: round(float(v), 3) for p, v in ph.items()},
         "per_step": {"walks": per_launch_walks, "walk_steps": per_launch_steps,
                      "edge_ops": sum(s["edge_ops"] for s in stats0),
                      "rounds_max": max(s["rounds"] for s in stats0)},

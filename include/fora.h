@@ -107,6 +107,8 @@ typedef struct fora_tuning {
   int32_t pull_ratio;         /* a query's push round runs as a pull over the
                                  reverse graph when its frontier edges times
                                  this exceed n + m (0: never pull)               */
+  int32_t walk_agg;           /* 1: waves sum walk end points in LDS before
+                                 adding them to HBM (same results)               */
 } fora_tuning;
 
 const char *fora_last_error(void);

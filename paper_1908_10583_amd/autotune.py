@@ -2,7 +2,8 @@
 
 It times real batched calls on the caller's graph and queries with the
 library's own per-phase HIP-event timers, picks the fastest shape phase by
-phase (pull/push switch point, push grid, then walk grid x walk chunk), decides whether replaying a
+phase (pull/push switch point, push grid, then walk grid x walk chunk x
+end-point aggregation), decides whether replaying a
 captured HIP graph beats the host-driven push loop, and caches the result in
 a JSON file keyed by device, graph size and batch size. Results never depend
 on the tuning; only speed does.
@@ -21,6 +22,7 @@ PULL_RATIOS = (0, 4, 16, 64)
 PUSH_BLOCKS = (2, 4, 8, 16)
 WALK_BLOCKS = (4, 8, 12, 16)
 WALK_CHUNKS = (256, 512, 1024, 2048)
+WALK_AGG = (0, 1)
 
 
 def cache_path() -> str:
@@ -97,14 +99,16 @@ def autotune(G: fora.Graph, queries, path: str | None = None, force: bool = Fals
             best_push = (pb, m["push"], m["rounds"])
     base["push_blocks_per_cu"] = best_push[0]
     best_walk = None
-    for wb in WALK_BLOCKS:
-        for ch in WALK_CHUNKS:
-            G.set_tuning(**dict(base, walk_blocks_per_cu=wb, walk_chunk=ch))
-            m = _timed(G, queries, ws, out)
-            trials.append(dict(walk_blocks_per_cu=wb, walk_chunk=ch, **m))
-            if best_walk is None or m["walk"] < best_walk[2]:
-                best_walk = (wb, ch, m["walk"])
+    for agg in WALK_AGG:
+        for wb in WALK_BLOCKS:
+            for ch in WALK_CHUNKS:
+                G.set_tuning(**dict(base, walk_blocks_per_cu=wb, walk_chunk=ch, walk_agg=agg))
+                m = _timed(G, queries, ws, out)
+                trials.append(dict(walk_blocks_per_cu=wb, walk_chunk=ch, walk_agg=agg, **m))
+                if best_walk is None or m["walk"] < best_walk[2]:
+                    best_walk = (wb, ch, m["walk"], agg)
     base["walk_blocks_per_cu"], base["walk_chunk"] = best_walk[0], best_walk[1]
+    base["walk_agg"] = best_walk[3]
     G.set_tuning(**base)
     eager = _timed(G, queries, ws, out, reps=3)
     rounds = int(best_push[2] * 1.25) + 4

@@ -35,7 +35,7 @@ struct fora_graph {
   std::mutex mu;
   uint64_t* pinned = nullptr;
   std::vector<int> free_slots;
-  fora_tuning tuning{8, 512, 4, 0, fora::kPullRatio};
+  fora_tuning tuning{8, 512, 4, 0, fora::kPullRatio, 0};
   std::mutex graph_mu;
   std::list<CapturedGraph> graphs;  // most recently used first
 };
@@ -258,7 +258,7 @@ hipError_t enqueue_pipeline(fora_graph* g, const Call& c, int batch, int rounds,
                           nullptr, 0, s);
   if (e == hipSuccess) e = launch_push_gate(c.w, rounds, s);
   if (e == hipSuccess) e = launch_plan(g->dev, c.w, c.L, batch, s);
-  if (e == hipSuccess) e = launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), s);
+  if (e == hipSuccess) e = launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), g->tuning.walk_agg != 0, s);
   if (e == hipSuccess) e = launch_topk(g->dev, c.w, c.L, batch, kmax, d_ids, d_vals, s);
   return e;
 }
@@ -328,7 +328,7 @@ int run_queries_graph(fora_graph* g, const Call& c, int batch, const std::vector
     rc = run_push(g, c, batch, s, true, nullptr, 0, nullptr, g->tuning.graph_rounds);
     if (rc != FORA_OK) return rc;
     FORA_HIP(launch_plan(g->dev, c.w, c.L, batch, s));
-    FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), s));
+    FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), g->tuning.walk_agg != 0, s));
     FORA_HIP(launch_topk(g->dev, c.w, c.L, batch, kmax, d_ids, d_vals, s));
   }
   return finish(g, c, batch, s, h_stats, qd, nullptr);
@@ -363,7 +363,7 @@ int run_queries(fora_graph* g, int batch, const fora_query* qs, int kmax, void* 
   pe.mark(1, s);
   FORA_HIP(launch_plan(g->dev, c.w, c.L, batch, s));
   pe.mark(2, s);
-  FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), s));
+  FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), g->tuning.walk_agg != 0, s));
   pe.mark(3, s);
   FORA_HIP(launch_topk(g->dev, c.w, c.L, batch, kmax, d_ids, d_vals, s));
   pe.mark(4, s);
@@ -660,6 +660,7 @@ int fora_set_tuning(fora_graph* g, const fora_tuning* t) {
   if (t->graph_rounds < 0 || t->graph_rounds > kMaxRoundsLogged)
     return fail(FORA_E_ARG, "graph_rounds must be in [0, 4096]");
   if (t->pull_ratio < 0) return fail(FORA_E_ARG, "pull_ratio must be >= 0");
+  if (t->walk_agg != 0 && t->walk_agg != 1) return fail(FORA_E_ARG, "walk_agg must be 0 or 1");
   drop_graphs(g);
   g->tuning = *t;
   return FORA_OK;
@@ -802,7 +803,7 @@ int fora_walk_only(const fora_graph* gc, int64_t entries, const int32_t* d_v,
   FORA_HIP(hipMemcpyAsync(c.w.queries, &qd, sizeof(qd), hipMemcpyHostToDevice, s));
   if (entries > 0) {
     FORA_HIP(launch_walk_plan_from_host(g->dev, c.w, entries, d_v, d_omega, d_w, s));
-    FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), s));
+    FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), g->tuning.walk_agg != 0, s));
   }
   std::vector<QueryDev> qv(1, qd);
   fora_stats st{};

@@ -195,7 +195,8 @@ hipError_t launch_push_round(const GraphDev& g, const Ws& w, const Layout& L, in
                              int64_t log_cap, hipStream_t s);
 hipError_t launch_plan(const GraphDev& g, const Ws& w, const Layout& L, int batch,
                        hipStream_t s);
-hipError_t launch_walks(const GraphDev& g, const Ws& w, int blocks, int chunk, hipStream_t s);
+hipError_t launch_walks(const GraphDev& g, const Ws& w, int blocks, int chunk, bool agg,
+                        hipStream_t s);
 hipError_t launch_push_gate(const Ws& w, int rounds, hipStream_t s);
 hipError_t launch_walk_plan_from_host(const GraphDev& g, const Ws& w, int64_t entries,
                                       const int32_t* d_v, const uint64_t* d_omega,

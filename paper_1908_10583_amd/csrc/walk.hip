@@ -8,6 +8,13 @@
 // floor(U * d(x) / 2^64) of x, where U = word1 * 2^32 + word2. At its end
 // point t it adds 1 to cnt[t] and its entry's fixed-point weight to acc[t].
 //
+// With AGG, a wave first adds its end points to a wave-private LDS table
+// keyed by (query, node) and moves the table's sums to HBM when it holds
+// kAggFlushAt keys and at the end; repeated end points (walks from one start
+// node that stop there or at its few neighbours) then cost one HBM atomic
+// pair per flush instead of one per walk. The sums are integers, so the
+// result is the same either way.
+//
 // Moves read the walk records (GraphDev): one step loads the chosen
 // neighbour's record start from the current record and then that
 // neighbour's 8-byte header (degree, id), so a step on a low-degree node
@@ -27,6 +34,53 @@
 namespace fora {
 
 constexpr int kWalkBlock = 256;
+constexpr int kWalkWaves = kWalkBlock / 64;
+// end-point aggregation: a wave-private LDS table of (query, node) keys
+constexpr int kAggSlots = 256;
+constexpr int kAggProbes = 4;
+constexpr int kAggFlushAt = 160;  // keys held before the wave flushes its table
+constexpr u64 kAggEmpty = ~0ull;
+
+struct AggTable {
+  u64* key;
+  u64* cnt;
+  u64* acc;
+};
+
+// Adds one end point to the wave's table; false if no slot was found within
+// kAggProbes probes (the caller then adds it to HBM directly). *fresh is set
+// when the key took a new slot.
+__device__ __forceinline__ bool agg_add(const AggTable& t, u64 gi, u64 wfx, bool* fresh) {
+  uint32_t h = (uint32_t)(gi * 0x9E3779B97F4A7C15ull >> 56);  // 8-bit multiplicative hash
+  for (int p = 0; p < kAggProbes; ++p) {
+    const uint32_t s = (h + (uint32_t)p) & (kAggSlots - 1);
+    const u64 old = atomicCAS(&t.key[s], kAggEmpty, gi);
+    if (old == kAggEmpty || old == gi) {
+      *fresh = old == kAggEmpty;
+      atomicAdd(&t.cnt[s], 1ull);
+      atomicAdd(&t.acc[s], wfx);
+      return true;
+    }
+  }
+  return false;
+}
+
+// Wave-uniform: moves every held key to HBM and empties the table.
+__device__ __forceinline__ void agg_flush(const AggTable& t, u64* __restrict__ cnt,
+                                          u64* __restrict__ acc) {
+  __builtin_amdgcn_wave_barrier();
+  for (int s = threadIdx.x & 63; s < kAggSlots; s += 64) {
+    const u64 k = t.key[s];
+    if (k != kAggEmpty) {
+      atomicAdd(&cnt[k], t.cnt[s]);
+      atomicAdd(&acc[k], t.acc[s]);
+      t.key[s] = kAggEmpty;
+      t.cnt[s] = 0;
+      t.acc[s] = 0;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
 
 // Largest e in [0, E) with off[e] <= target, by 64-way probing (wave-uniform).
 __device__ __forceinline__ u64 wave_find_entry(const u64* __restrict__ off, u64 E, u64 target) {
@@ -48,12 +102,14 @@ __device__ __forceinline__ u64 wave_find_entry(const u64* __restrict__ off, u64 
   return lo + (u64)(63 - __builtin_clzll(mask));
 }
 
+template <bool AGG>
 __global__ __launch_bounds__(kWalkBlock) void k_walks(
     const u64* __restrict__ plan_gi, const u64* __restrict__ plan_off,
     const u64* __restrict__ plan_wfx, Ctrl* ctrl, const QueryDev* __restrict__ Q,
     QueryStatsDev* QS, const int2* __restrict__ info, const uint32_t* __restrict__ rec,
     const uint32_t* __restrict__ rec_q, int n, u64* __restrict__ cnt, u64* __restrict__ acc,
     int chunk) {
+  __shared__ u64 s_agg[AGG ? 3 * kWalkWaves * kAggSlots : 1];
   if (ctrl->error || ctrl->skip) return;
   const u64 W = ctrl->walks;
   const u64 E = ctrl->entries;
@@ -61,6 +117,18 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
   const int lane = threadIdx.x & 63;
   const int slot = (int)(((blockIdx.x << 2) + (threadIdx.x >> 6)) & (kStatSlots - 1));
 
+  AggTable agg{};
+  unsigned agg_fill = 0;  // wave-uniform count of keys in the table
+  if (AGG) {
+    u64* base = s_agg + (size_t)(threadIdx.x >> 6) * 3 * kAggSlots;
+    agg = AggTable{base, base + kAggSlots, base + 2 * kAggSlots};
+    for (int s = lane; s < kAggSlots; s += 64) {
+      agg.key[s] = kAggEmpty;
+      agg.cnt[s] = 0;
+      agg.acc[s] = 0;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
   bool active = false;
   int b = 0;
   uint32_t v = 0, j = 0, step = 0, k0 = 0, k1 = 0, ta = 0;
@@ -142,12 +210,19 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
       if (!more) break;
       continue;
     }
+    if (AGG && agg_fill > kAggFlushAt) {
+      agg_flush(agg, cnt, acc);
+      agg_fill = 0;
+    }
+    bool fresh = false;
     if (active) {
       const uint4 y = philox4x32_10(make_uint4(v, j, step, 0u), k0, k1);
       if (y.x < ta) {
         const size_t t = (size_t)b * n + x;
-        atomicAdd(&cnt[t], 1ull);
-        atomicAdd(&acc[t], wfx);
+        if (!AGG || !agg_add(agg, (u64)t, wfx, &fresh)) {
+          atomicAdd(&cnt[t], 1ull);
+          atomicAdd(&acc[t], wfx);
+        }
         if (b != stat_b) {
           if (stat_b >= 0) atomicAdd(&QS[(size_t)stat_b * kStatSlots + slot].steps, stat_steps);
           stat_b = b;
@@ -166,7 +241,9 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
         ++step;
       }
     }
+    if (AGG) agg_fill += (unsigned)__popcll(__ballot(fresh));
   }
+  if (AGG) agg_flush(agg, cnt, acc);
   // per-query step totals: one atomic per wave when the wave saw one query
   const int b0 = __shfl(stat_b, 0, 64);
   const u64 mine = (stat_b == b0) ? stat_steps : 0ull;
@@ -176,10 +253,16 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
     atomicAdd(&QS[(size_t)stat_b * kStatSlots + slot].steps, stat_steps);
 }
 
-hipError_t launch_walks(const GraphDev& g, const Ws& w, int blocks, int chunk, hipStream_t s) {
-  k_walks<<<blocks, kWalkBlock, 0, s>>>(w.plan_gi, w.plan_off, w.plan_wfx, w.ctrl, w.queries,
-                                        w.qstats, g.info, g.rec, g.rec_q, g.n, w.cnt, w.acc,
-                                        chunk);
+hipError_t launch_walks(const GraphDev& g, const Ws& w, int blocks, int chunk, bool agg,
+                        hipStream_t s) {
+  if (agg)
+    k_walks<true><<<blocks, kWalkBlock, 0, s>>>(w.plan_gi, w.plan_off, w.plan_wfx, w.ctrl,
+                                                w.queries, w.qstats, g.info, g.rec, g.rec_q, g.n,
+                                                w.cnt, w.acc, chunk);
+  else
+    k_walks<false><<<blocks, kWalkBlock, 0, s>>>(w.plan_gi, w.plan_off, w.plan_wfx, w.ctrl,
+                                                 w.queries, w.qstats, g.info, g.rec, g.rec_q,
+                                                 g.n, w.cnt, w.acc, chunk);
   return hipGetLastError();
 }
 

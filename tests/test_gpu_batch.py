@@ -60,7 +60,7 @@ def test_tuning_validation(G1k):
     t = G1k.get_tuning()
     assert t["walk_chunk"] % 64 == 0 and t["graph_rounds"] == 0
     for bad in (dict(walk_chunk=100), dict(walk_chunk=0), dict(walk_blocks_per_cu=0),
-                dict(push_blocks_per_cu=99), dict(graph_rounds=-1)):
+                dict(push_blocks_per_cu=99), dict(graph_rounds=-1), dict(walk_agg=2)):
         with pytest.raises(fora.FORAError) as ei:
             G1k.set_tuning(**bad)
         assert ei.value.code == fora.FORA_E_ARG
@@ -69,7 +69,8 @@ def test_tuning_validation(G1k):
 
 @pytest.mark.parametrize("shape", [dict(walk_blocks_per_cu=1, walk_chunk=64, push_blocks_per_cu=1),
                                    dict(walk_blocks_per_cu=16, walk_chunk=4096,
-                                        push_blocks_per_cu=16)])
+                                        push_blocks_per_cu=16),
+                                   dict(walk_blocks_per_cu=4, walk_chunk=512, walk_agg=1)])
 def test_results_do_not_depend_on_tuning(g1k, G1k, shape):
     ref = oracle.fora(g1k, 7, k=50, seed=3)
     G1k.set_tuning(**shape)

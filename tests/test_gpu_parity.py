@@ -244,6 +244,26 @@ def test_walk_parity_random_plans(grmat12, Grmat12, entries, max_walks, seed):
     _walk_compare(grmat12, Grmat12, pv, po, pw, 11 + seed, 99)
 
 
+@pytest.mark.parametrize("entries,max_walks,seed,chunk", [(1, 100000, 1, 64), (3000, 300, 4, 512),
+                                                          (64, 513, 5, 4096), (4096, 1, 3, 256)])
+def test_walk_parity_with_lds_aggregation(grmat12, Grmat12, entries, max_walks, seed, chunk):
+    # end points summed in the waves' LDS tables first: counts and fixed-point
+    # weights are integer sums, so they equal the direct path bit for bit
+    pv, po, pw = synth.random_walk_plan(grmat12, entries, max_walks, seed)
+    t0 = Grmat12.get_tuning()
+    try:
+        Grmat12.set_tuning(walk_agg=0, walk_chunk=chunk)
+        direct = fora.fora_walk_only(Grmat12, pv, po, pw, 11 + seed, 99, ALPHA)
+        d_cnt, d_acc = _cnt(direct["cnt"]).copy(), _u64(direct["acc_fx"]).copy()
+        Grmat12.set_tuning(walk_agg=1, walk_chunk=chunk)
+        _, got = _walk_compare(grmat12, Grmat12, pv, po, pw, 11 + seed, 99)
+        assert np.array_equal(_cnt(got["cnt"]), d_cnt)
+        assert np.array_equal(_u64(got["acc_fx"]), d_acc)
+        assert got["steps"] == direct["steps"]
+    finally:
+        Grmat12.set_tuning(**t0)
+
+
 def test_walk_only_empty_plan(G1k):
     got = fora.fora_walk_only(G1k, np.zeros(0, np.int32), np.zeros(0, np.uint64),
                               np.zeros(0), 0, 0, ALPHA)
