@@ -78,6 +78,9 @@ def main():
                     help="queries per batched call (0: all sources in one call)")
     ap.add_argument("--single-sample", type=int, default=0,
                     help="sources timed by the plain single-query loop (0: all)")
+    ap.add_argument("--sources", type=int, default=0,
+                    help="use only the workload's first N sources (0: all)")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy, whose HBM counter "
                          "readings calibrate FETCH_SIZE / WRITE_SIZE")
@@ -93,6 +96,8 @@ def main():
     alpha, eps, k, seed = 0.2, 0.5, 500, 0
     t0 = time.perf_counter()
     g, srcs = synth.workload(args.workload)
+    if args.sources:
+        srcs = srcs[:args.sources]
     log(f"graph {g.name}: n={g.n} m={g.m} sources={len(srcs)} ({time.perf_counter()-t0:.1f}s)")
     G = fora.Graph.from_numpy(g.rowptr, g.colidx, device="cuda:0")
     B = len(srcs)
@@ -207,7 +212,7 @@ def main():
         log(f"batched + learned r_max: {B * args.steps / dtl:.1f} q/s")
 
     graph_mode = None
-    if graph_rounds > 0:
+    if graph_rounds > 0 and not args.no_graph:
         G.set_tuning(graph_rounds=graph_rounds)
         run_all()  # capture
         torch.cuda.synchronize()

@@ -33,7 +33,9 @@ def cache_path() -> str:
 def _key(G: fora.Graph, batch: int) -> str:
     props = torch.cuda.get_device_properties(G.device)
     bucket = 1 << max(0, (batch - 1).bit_length())
-    return f"{props.name}|cu={props.multi_processor_count}|n={G.n}|m={G.m}|batch<={bucket}"
+    # the architecture name, not the marketing name (which some tools blank)
+    arch = getattr(props, "gcnArchName", "") or props.name
+    return f"{arch}|cu={props.multi_processor_count}|n={G.n}|m={G.m}|batch<={bucket}"
 
 
 def _load(path: str) -> dict:

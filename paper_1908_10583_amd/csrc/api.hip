@@ -29,6 +29,7 @@ struct fora_graph {
   fora::u64* inhub_base_owned = nullptr;
   uint32_t* rec_owned = nullptr;
   uint32_t* rec_q_owned = nullptr;
+  int32_t* rank_owned = nullptr;
   int device = 0;
   int cus = 256;
   // pinned host slots for the small read-backs of the push loop
@@ -547,6 +548,26 @@ int build_reverse(fora_graph* g, hipStream_t s) {
   return FORA_OK;
 }
 
+// Degree rank of every node (GraphDev::rank).
+int build_rank(fora_graph* g, hipStream_t s) {
+  const int32_t n = g->dev.n;
+  size_t bytes = 0;
+  if (degree_rank_scratch_bytes(n, &bytes) != hipSuccess)
+    return fail(FORA_E_HIP, "degree rank: sort sizing failed");
+  void* scratch = nullptr;
+  if (hipMalloc(&g->rank_owned, sizeof(int32_t) * (size_t)n) != hipSuccess ||
+      hipMalloc(&scratch, bytes) != hipSuccess) {
+    if (scratch) (void)hipFree(scratch);
+    return fail(FORA_E_NOMEM, "hipMalloc of the degree rank failed");
+  }
+  g->dev.rank = g->rank_owned;
+  hipError_t e = launch_degree_rank(g->dev, g->rank_owned, scratch, bytes, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(scratch);
+  if (e != hipSuccess) return fail(FORA_E_HIP, std::string("degree rank: ") + hipGetErrorString(e));
+  return FORA_OK;
+}
+
 // Walk records (one 8-byte header plus one word per out-edge per node).
 int build_records(fora_graph* g, hipStream_t s) {
   const int64_t n = g->dev.n;
@@ -560,7 +581,7 @@ int build_records(fora_graph* g, hipStream_t s) {
   };
   if (hipMalloc(&g->rec_owned, sizeof(uint32_t) * (size_t)words) != hipSuccess ||
       hipMalloc(&g->rec_q_owned, sizeof(uint32_t) * ((size_t)n + 1)) != hipSuccess ||
-      hipMalloc(&tmp, sizeof(int32_t) * (size_t)n) != hipSuccess ||
+      hipMalloc(&tmp, sizeof(int32_t) * (2 * (size_t)n + 1)) != hipSuccess ||
       hipMalloc(&tsum, sizeof(uint32_t) * (size_t)tiles) != hipSuccess) {
     release();
     return fail(FORA_E_NOMEM, "hipMalloc of the walk records failed");
@@ -600,6 +621,7 @@ int fora_build_csr(int32_t n, int64_t m, const int32_t* d_rowptr, const int32_t*
     if (g->inhub_base_owned) (void)hipFree(g->inhub_base_owned);
     if (g->rec_owned) (void)hipFree(g->rec_owned);
     if (g->rec_q_owned) (void)hipFree(g->rec_q_owned);
+    if (g->rank_owned) (void)hipFree(g->rank_owned);
     if (g->info_owned) (void)hipFree(g->info_owned);
     if (g->flags_owned) (void)hipFree(g->flags_owned);
     if (g->pinned) (void)hipHostFree(g->pinned);
@@ -633,7 +655,8 @@ int fora_build_csr(int32_t n, int64_t m, const int32_t* d_rowptr, const int32_t*
     return cleanup(FORA_E_GRAPH, "a node has out-degree 0 (dangling)");
   g->dev.max_deg = host_flags[1];
   g->dev.n_hubs = host_flags[2];
-  int rrc = build_reverse(g, s);
+  int rrc = build_rank(g, s);
+  if (rrc == FORA_OK) rrc = build_reverse(g, s);
   if (rrc == FORA_OK) rrc = build_records(g, s);
   if (rrc != FORA_OK) {
     const std::string msg = g_err;
@@ -675,6 +698,7 @@ int fora_free_graph(fora_graph* g) {
   if (g->inhub_base_owned) (void)hipFree(g->inhub_base_owned);
   if (g->rec_owned) (void)hipFree(g->rec_owned);
   if (g->rec_q_owned) (void)hipFree(g->rec_q_owned);
+  if (g->rank_owned) (void)hipFree(g->rank_owned);
   if (g->info_owned) (void)hipFree(g->info_owned);
   if (g->flags_owned) (void)hipFree(g->flags_owned);
   if (g->pinned) (void)hipHostFree(g->pinned);

@@ -1,5 +1,7 @@
 // Graph ingest checks, the per-node {row start, out-degree} table, a zero
 // fill, and the device Philox block kernel used for RNG checks.
+#include <hipcub/hipcub.hpp>
+
 #include "internal.h"
 #include "scan.h"
 
@@ -148,12 +150,13 @@ __global__ __launch_bounds__(256) void k_tile_apply(const int32_t* __restrict__ 
 }
 
 __global__ void k_fill_rev(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
-                           int32_t n, int32_t* cursor, int32_t* in_colidx) {
+                           const int32_t* __restrict__ rank, int32_t n, int32_t* cursor,
+                           int32_t* in_colidx) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x)
     for (int32_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
       const int32_t pos = atomicAdd(&cursor[colidx[e]], 1);
-      in_colidx[pos] = (int32_t)v;
+      in_colidx[pos] = rank[v];  // in-neighbours are stored by degree rank
     }
 }
 
@@ -182,17 +185,71 @@ hipError_t launch_build_reverse(const GraphDev& g, int32_t* in_rowptr, int32_t* 
   k_tile_scan<<<1, 1024, 0, s>>>(tsum, tiles);
   // in_rowptr and the fill cursor both start as the exclusive prefix
   k_tile_apply<<<(unsigned)tiles, 256, 0, s>>>(cursor, n, tsum, in_rowptr, cursor);
-  if (m > 0) k_fill_rev<<<bn, 256, 0, s>>>(g.rowptr, g.colidx, g.n, cursor, in_colidx);
+  if (m > 0) k_fill_rev<<<bn, 256, 0, s>>>(g.rowptr, g.colidx, g.rank, g.n, cursor, in_colidx);
+  return hipGetLastError();
+}
+
+// Degree rank: sort (out-degree, id) pairs by degree, descending (the sort is
+// stable, so equal degrees keep id order), then rank[order[i]] = i.
+__global__ void k_deg_keys(const int2* __restrict__ info, int32_t n, int32_t* key, int32_t* id) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    key[v] = info[v].y;
+    id[v] = (int32_t)v;
+  }
+}
+
+__global__ void k_rank_from_order(const int32_t* __restrict__ order, int32_t n, int32_t* rank) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    rank[order[i]] = (int32_t)i;
+}
+
+hipError_t degree_rank_scratch_bytes(int32_t n, size_t* bytes) {
+  size_t sort_bytes = 0;
+  const hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(
+      nullptr, sort_bytes, (const int32_t*)nullptr, (int32_t*)nullptr, (const int32_t*)nullptr,
+      (int32_t*)nullptr, n);
+  *bytes = 4 * sizeof(int32_t) * (size_t)n + 256 + sort_bytes;
+  return e;
+}
+
+hipError_t launch_degree_rank(const GraphDev& g, int32_t* rank, void* scratch,
+                              size_t scratch_bytes, hipStream_t s) {
+  const int64_t n = g.n;
+  int32_t* key_in = (int32_t*)scratch;
+  int32_t* key_out = key_in + n;
+  int32_t* id_in = key_out + n;
+  int32_t* id_out = id_in + n;
+  const size_t used = 4 * sizeof(int32_t) * (size_t)n;
+  void* sort_tmp = (char*)scratch + ((used + 255) / 256) * 256;
+  size_t sort_bytes = scratch_bytes - ((used + 255) / 256) * 256;
+  const int bn = (int)std::min<int64_t>((n + 255) / 256, 16384);
+  k_deg_keys<<<bn, 256, 0, s>>>(g.info, g.n, key_in, id_in);
+  hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(
+      sort_tmp, sort_bytes, key_in, key_out, id_in, id_out, (int)n, 0, 32, s);
+  if (e != hipSuccess) return e;
+  k_rank_from_order<<<bn, 256, 0, s>>>(id_out, g.n, rank);
   return hipGetLastError();
 }
 
 // Walk records (see GraphDev): record lengths in 8-byte units, their
 // exclusive prefix (the record starts), then one wavefront per node fills a
 // record: lane 0 the header, all lanes the neighbours' record starts.
-__global__ void k_rec_len(const int2* __restrict__ info, int32_t n, int32_t* len) {
+__global__ void k_rec_len(const int2* __restrict__ info, const int32_t* __restrict__ rank,
+                          int32_t n, int32_t* len) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x)
-    len[v] = (2 + info[v].y + 1) / 2;
+    len[rank[v]] = (2 + info[v].y + 1) / 2;
+}
+
+// rec_q[v] = start[rank[v]] (start holds the record starts in rank order)
+__global__ void k_rec_start(const int32_t* __restrict__ rank, int32_t n,
+                            const uint32_t* __restrict__ start, uint32_t* rec_q) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    rec_q[v] = start[rank[v]];
+  if (blockIdx.x == 0 && threadIdx.x == 0) rec_q[n] = start[n];
 }
 
 __global__ void k_fill_rec(const int2* __restrict__ info, const int32_t* __restrict__ colidx,
@@ -212,16 +269,19 @@ __global__ void k_fill_rec(const int2* __restrict__ info, const int32_t* __restr
   }
 }
 
+// tmp: 2n + 1 int32 of scratch.
 hipError_t launch_build_records(const GraphDev& g, uint32_t* rec_q, uint32_t* rec, int32_t* tmp,
                                 uint32_t* tsum, hipStream_t s) {
   const int64_t n = g.n;
   const int64_t tiles = (n + kScanTile - 1) / kScanTile;
   const int bn = (int)std::min<int64_t>((n + 255) / 256, 16384);
-  k_rec_len<<<bn, 256, 0, s>>>(g.info, g.n, tmp);
-  k_tile_sum<<<(unsigned)tiles, 256, 0, s>>>(tmp, n, tsum);
+  int32_t* len = tmp;            // record lengths in rank order
+  int32_t* start = tmp + n;      // their exclusive prefix, n + 1 entries
+  k_rec_len<<<bn, 256, 0, s>>>(g.info, g.rank, g.n, len);
+  k_tile_sum<<<(unsigned)tiles, 256, 0, s>>>(len, n, tsum);
   k_tile_scan<<<1, 1024, 0, s>>>(tsum, tiles);
-  // the starts go to rec_q (rec_q[n] = total units); tmp is reused as scratch
-  k_tile_apply<<<(unsigned)tiles, 256, 0, s>>>(tmp, n, tsum, (int32_t*)rec_q, tmp);
+  k_tile_apply<<<(unsigned)tiles, 256, 0, s>>>(len, n, tsum, start, len);
+  k_rec_start<<<bn, 256, 0, s>>>(g.rank, g.n, (const uint32_t*)start, rec_q);
   const int wb = (int)std::min<int64_t>((n + 3) / 4, 65536);
   k_fill_rec<<<wb, 256, 0, s>>>(g.info, g.colidx, g.n, rec_q, rec);
   return hipGetLastError();

@@ -111,6 +111,10 @@ struct GraphDev {
   // (padded to an even word count)
   const uint32_t* rec;
   const uint32_t* rec_q;
+  // rank of each node by out-degree, descending (ties by id): the slot of v
+  // in the dense pull-increment rows, and the order of the walk records, so
+  // that the values read most often (those of high-degree nodes) share lines
+  const int32_t* rank;
 };
 
 struct Layout {
@@ -207,6 +211,10 @@ hipError_t launch_build_reverse(const GraphDev& g, int32_t* in_rowptr, int32_t* 
                                 int32_t* cursor, uint32_t* tsum, hipStream_t s);
 hipError_t launch_build_records(const GraphDev& g, uint32_t* rec_q, uint32_t* rec, int32_t* tmp,
                                 uint32_t* tsum, hipStream_t s);
+// rank[v] from the out-degrees; scratch: 4 int32 arrays of n and sort storage
+hipError_t degree_rank_scratch_bytes(int32_t n, size_t* bytes);
+hipError_t launch_degree_rank(const GraphDev& g, int32_t* rank, void* scratch,
+                              size_t scratch_bytes, hipStream_t s);
 hipError_t launch_list_inhubs(const int32_t* in_rowptr, int32_t n, int32_t* list, int32_t* count,
                               int32_t cap, hipStream_t s);
 hipError_t launch_seed_frontier(const GraphDev& g, const Ws& w, const Layout& L, int batch, int t,

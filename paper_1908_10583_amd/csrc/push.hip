@@ -18,6 +18,9 @@
 // * pull (dense rounds, frontier edges * kPullRatio > n + m): every node sums
 //   the dense increments of its in-neighbours over the reverse graph (LDS
 //   accumulation, no atomics to HBM), then updates r(u) once and tests it.
+//   The dense increments sit at each node's degree rank (GraphDev::rank),
+//   and the reverse graph stores in-neighbours by rank, so the gathers of
+//   high-degree nodes' increments (the most frequent ones) share lines.
 //   Nodes of in-degree above kHubDeg are summed in pieces by any block and
 //   added with one atomic per piece.
 #include "internal.h"
@@ -52,7 +55,8 @@ __global__ __launch_bounds__(256) void k_push_snapshot(
     int t, Ctrl* ctrl, const u64* __restrict__ fr_in, float* __restrict__ frx,
     float* __restrict__ r, float* __restrict__ q, float* __restrict__ incd,
     const QueryDev* __restrict__ Q, StatSlot* slots, u64* ecnt, const int2* __restrict__ info,
-    int n, int batch, int32_t* frontier_log, int64_t log_cap, u64 cap, u64* hub_idx,
+    const int32_t* __restrict__ rank, int n, int batch, int32_t* frontier_log, int64_t log_cap,
+    u64 cap, u64* hub_idx,
     u64* hub_base, u64 hub_cap) {
   extern __shared__ unsigned char smem[];
   u64* s_edges = (u64*)smem;
@@ -82,7 +86,7 @@ __global__ __launch_bounds__(256) void k_push_snapshot(
     const int d = info[v].y;
     const float inc = (float)(((1.0 - alpha) * (double)x) / (double)d);
     frx[i] = inc;
-    incd[gi] = inc;
+    incd[(size_t)b * n + rank[v]] = inc;
     if (d > kHubDeg) {
       const u64 pieces = (u64)((d + kHubPiece - 1) / kHubPiece);
       const u64 old = atomicAdd(&ctrl->hub_ctr[t & 1], (1ull << 40) | pieces);
@@ -297,8 +301,9 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
     int t, Ctrl* ctrl, const u64* __restrict__ fr_in, const float* __restrict__ frx,
     u64* __restrict__ fr_out, u64 cap, float* __restrict__ r, float* __restrict__ incd,
     const int32_t* __restrict__ mode, const QueryDev* __restrict__ Q,
-    const int2* __restrict__ info, const int32_t* __restrict__ colidx, int n,
-    const u64* __restrict__ hub_idx, const u64* __restrict__ hub_base, u64 hub_cap) {
+    const int2* __restrict__ info, const int32_t* __restrict__ colidx,
+    const int32_t* __restrict__ rank, int n, const u64* __restrict__ hub_idx,
+    const u64* __restrict__ hub_base, u64 hub_cap) {
   __shared__ u64 s_pre[kScatterBlock];
   __shared__ int32_t s_start[kScatterBlock];
   __shared__ uint32_t s_ent_b[kScatterBlock];
@@ -324,7 +329,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
   for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
        i += (u64)gridDim.x * blockDim.x) {
     const u64 e = fr_in[i];
-    incd[(size_t)(e >> 32) * n + (uint32_t)e] = 0.0f;
+    incd[(size_t)(e >> 32) * n + rank[(uint32_t)e]] = 0.0f;
   }
   __syncthreads();
 
@@ -441,7 +446,8 @@ hipError_t launch_push_round(const GraphDev& g, const Ws& w, const Layout& L, in
   const size_t smem = (size_t)batch * (sizeof(u64) + sizeof(uint32_t));
   const u64 cap = (u64)L.cap;
   k_push_snapshot<<<blocks, 256, smem, s>>>(t, w.ctrl, w.fr[par], w.frx, w.r, w.q, w.incd,
-                                            w.queries, w.qstats, w.ecnt, g.info, g.n, batch,
+                                            w.queries, w.qstats, w.ecnt, g.info, g.rank, g.n,
+                                            batch,
                                             frontier_log, log_cap, cap, w.hub_idx, w.hub_base,
                                             (u64)L.hub_cap);
   k_push_mode<<<1, 256, 0, s>>>(t, w.ctrl, w.ecnt, w.mode, w.pull_list, w.qstats, batch,
@@ -452,7 +458,7 @@ hipError_t launch_push_round(const GraphDev& g, const Ws& w, const Layout& L, in
                                                g.n_inhubs, g.inhub_pieces, g.n);
   k_push_scatter<<<blocks, kScatterBlock, 0, s>>>(t, w.ctrl, w.fr[par], w.frx, w.fr[par ^ 1],
                                                   cap, w.r, w.incd, w.mode, w.queries, g.info,
-                                                  g.colidx, g.n, w.hub_idx, w.hub_base,
+                                                  g.colidx, g.rank, g.n, w.hub_idx, w.hub_base,
                                                   (u64)L.hub_cap);
   return hipGetLastError();
 }
