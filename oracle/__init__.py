@@ -57,7 +57,10 @@ def _load():
     lib.oracle_push_continue.restype = i32
     lib.oracle_plan.argtypes = [i32, P, f64, P, P, P]
     lib.oracle_plan.restype = i64
-    lib.oracle_walks.argtypes = [i32, P, P, u32, u32, u32, i64, P, P, P, P, P, P, P]
+    lib.oracle_walks.argtypes = [i32, P, P, u32, u32, u32, i64, P, P, P, i32, P, P, P, P]
+    lib.oracle_push_balanced.argtypes = [i32, P, P, i32, f64, f64, f64, f64, P, P, i32, P, P,
+                                         P, i64, P, P, P]
+    lib.oracle_push_balanced.restype = i32
     lib.oracle_topk.argtypes = [i32, P, i32, P, P]
     lib.oracle_topk.restype = ctypes.c_int
     _lib = lib
@@ -173,9 +176,43 @@ def plan(r: np.ndarray, omega_unit: float):
     return pv[:e].copy(), po[:e].copy(), pw[:e].copy()
 
 
+def push_balanced(g, s: int, alpha: float, rmax: float, omega_unit: float, walk_cost: float,
+                  max_rounds: int = 100000, log_frontiers: bool = False) -> dict:
+    """Algorithm 3's push: synchronous Algorithm 1 that also stops once the
+    edge operations done reach the estimated walk cost,
+    (1 - alpha * pushed mass) (1 - alpha) omega_unit walk_cost."""
+    lib = _load()
+    rp, ci = _csr(g)
+    n = rp.shape[0] - 1
+    r = np.zeros(n, np.float64)
+    q = np.zeros(n, np.float64)
+    sizes = np.zeros(max_rounds, np.int32)
+    ops = np.zeros(1, np.int64)
+    margin = np.zeros(1, np.float64)
+    bmargin = np.zeros(1, np.float64)
+    stopped = np.zeros(1, np.int32)
+    cap = 64 * n if log_frontiers else 0
+    flog = np.zeros(cap, np.int32) if log_frontiers else None
+    rounds = lib.oracle_push_balanced(n, _p(rp), _p(ci), int(s), alpha, rmax, omega_unit,
+                                      float(walk_cost), _p(r), _p(q), max_rounds, _p(sizes),
+                                      _p(ops), _p(flog), cap, _p(margin), _p(bmargin),
+                                      _p(stopped))
+    if rounds < 0:
+        raise RuntimeError(f"oracle_push_balanced failed ({rounds})")
+    sizes = sizes[:rounds].copy()
+    out = dict(r=r, q=q, rounds=int(rounds), round_sizes=sizes, edge_ops=int(ops[0]),
+               min_margin=float(margin[0]), balance_margin=float(bmargin[0]),
+               stopped=bool(stopped[0]))
+    if log_frontiers:
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        out["frontiers"] = [flog[offs[i]:offs[i + 1]].copy() for i in range(rounds)]
+    return out
+
+
 def walks(g, source: int, seed: int, t_alpha: int, plan_v, plan_omega, plan_w,
-          endpoints: bool = False) -> dict:
-    """Run every planned walk; endpoint counts, weighted sums and step total."""
+          endpoints: bool = False, first_move: bool = False) -> dict:
+    """Run every planned walk; endpoint counts, weighted sums and step total.
+    first_move: every walk's first step is a forced move (Algorithm 3)."""
     lib = _load()
     rp, ci = _csr(g)
     n = rp.shape[0] - 1
@@ -188,8 +225,8 @@ def walks(g, source: int, seed: int, t_alpha: int, plan_v, plan_omega, plan_w,
     W = int(po.sum())
     ends = np.zeros(W, np.int32) if endpoints else None
     lib.oracle_walks(n, _p(rp), _p(ci), source & 0xFFFFFFFF, seed & 0xFFFFFFFF,
-                     t_alpha, pv.shape[0], _p(pv), _p(po), _p(pw), _p(cnt),
-                     _p(acc), _p(steps), _p(ends))
+                     t_alpha, pv.shape[0], _p(pv), _p(po), _p(pw), int(bool(first_move)),
+                     _p(cnt), _p(acc), _p(steps), _p(ends))
     out = dict(cnt=cnt, acc=acc, steps=int(steps[0]), walks=W)
     if endpoints:
         out["endpoints"] = ends
@@ -209,18 +246,31 @@ def topk(pi: np.ndarray, k: int):
 
 def fora(g, s: int, alpha: float = 0.2, eps: float = 0.5, delta: float | None = None,
          pf: float | None = None, k: int = 500, seed: int = 0,
-         rmax: float | None = None, log_frontiers: bool = False) -> dict:
-    """Whole-graph FORA (Algorithm 2) followed by top-k selection."""
+         rmax: float | None = None, log_frontiers: bool = False, prune: bool = False,
+         walk_cost: float | None = None) -> dict:
+    """Whole-graph FORA (Algorithm 2) followed by top-k selection.
+
+    prune: Algorithm 3's zero-hop pruning (section 5.1): pi_hat starts at
+    q + alpha r, and from each v with residue ceil(r'(v) omega_unit) walks
+    with r' = (1 - alpha) r start at a random out-neighbour of v, each adding
+    r'(v) / omega_v at its end point.
+    walk_cost: Algorithm 3's balance rule (section 5.2), the cost of one walk
+    in edge-operation units (None: plain Algorithm 1)."""
     n = g.n
     delta = 1.0 / n if delta is None else delta
     pf = 1.0 / n if pf is None else pf
     if validate(g) != 0:
         raise ValueError("invalid graph")
     c = constants(g.m, alpha, eps, delta, pf, rmax)
-    ps = push(g, s, alpha, c["rmax"], log_frontiers=log_frontiers)
-    pv, po, pw = plan(ps["r"], c["omega_unit"])
-    wk = walks(g, s, seed, c["t_alpha"], pv, po, pw)
-    pi = ps["q"] + wk["acc"]
+    if walk_cost is None:
+        ps = push(g, s, alpha, c["rmax"], log_frontiers=log_frontiers)
+    else:
+        ps = push_balanced(g, s, alpha, c["rmax"], c["omega_unit"], walk_cost,
+                           log_frontiers=log_frontiers)
+    r_walk = (1.0 - alpha) * ps["r"] if prune else ps["r"]
+    pv, po, pw = plan(r_walk, c["omega_unit"])
+    wk = walks(g, s, seed, c["t_alpha"], pv, po, pw, first_move=prune)
+    pi = ps["q"] + wk["acc"] + (alpha * ps["r"] if prune else 0.0)
     ids, vals = topk(pi, min(k, n))
     out = dict(consts=c, plan=(pv, po, pw), pi=pi, topk_ids=ids, topk_vals=vals,
                r_sum=float(ps["r"].sum()))

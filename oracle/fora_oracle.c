@@ -127,18 +127,27 @@ void oracle_constants(int64_t m, double alpha, double eps, double delta,
 /* ------------------------------------------------------------------------ */
 /* The push loop from a given (r, q), so that Algorithm 1 can be continued  */
 /* at a lower threshold from the state another threshold left.              */
-int32_t oracle_push_continue(int32_t n, const int32_t *rowptr,
-                             const int32_t *colidx, double alpha, double rmax,
-                             double *r, double *q, int32_t max_rounds,
-                             int32_t *round_sizes, int64_t *edge_ops,
-                             int32_t *frontier_log, int64_t frontier_cap,
-                             double *min_margin) {
+/* With walk_cost >= 0 it also applies the balance rule of Algorithm 3      */
+/* (section 5.2): before each round, with FC the edge operations done so    */
+/* far and r_sum = 1 - alpha * (mass pushed so far), it stops once          */
+/* FC >= r_sum (1 - alpha) omega_unit walk_cost, the estimated cost of the  */
+/* walks in edge-operation units. *balance_margin (if given) receives the   */
+/* smallest |FC - estimate| / estimate over the tests made; *stopped is 1   */
+/* if the rule ended the push.                                              */
+static int32_t push_core(int32_t n, const int32_t *rowptr, const int32_t *colidx,
+                         double alpha, double rmax, double *r, double *q,
+                         int32_t max_rounds, int32_t *round_sizes,
+                         int64_t *edge_ops, int32_t *frontier_log,
+                         int64_t frontier_cap, double *min_margin,
+                         double omega_unit, double walk_cost, double *balance_margin,
+                         int32_t *stopped) {
   int32_t *front = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
   double *x = (double *)malloc(sizeof(double) * (size_t)n);
   if (!front || !x) { free(front); free(x); return -3; }
   int32_t rounds = 0;
   int64_t ops = 0, logged = 0;
-  double margin = INFINITY;
+  double margin = INFINITY, bmargin = INFINITY, pushed = 0.0;
+  if (stopped) *stopped = 0;
   for (;;) {
     int32_t nf = 0;
     for (int32_t v = 0; v < n; ++v) {
@@ -151,6 +160,18 @@ int32_t oracle_push_continue(int32_t n, const int32_t *rowptr,
       if (r[v] > thr) front[nf++] = v;
     }
     if (nf == 0) break;
+    if (walk_cost >= 0.0) {
+      const double r_sum = 1.0 - alpha * pushed;
+      const double est = r_sum * (1.0 - alpha) * omega_unit * walk_cost;
+      if (est > 0.0) {
+        const double rel = fabs((double)ops - est) / est;
+        if (rel < bmargin) bmargin = rel;
+      }
+      if ((double)ops >= est) {
+        if (stopped) *stopped = 1;
+        break;
+      }
+    }
     if (rounds == max_rounds) { rounds = -1; break; }
     if (round_sizes) round_sizes[rounds] = nf;
     if (frontier_log) {
@@ -163,6 +184,7 @@ int32_t oracle_push_continue(int32_t n, const int32_t *rowptr,
       x[i] = r[v];
       r[v] = 0.0;
       q[v] += alpha * x[i];
+      pushed += x[i];
     }
     for (int32_t i = 0; i < nf; ++i) {
       int32_t v = front[i];
@@ -175,9 +197,36 @@ int32_t oracle_push_continue(int32_t n, const int32_t *rowptr,
   }
   if (edge_ops) *edge_ops = ops;
   if (min_margin) *min_margin = margin;
+  if (balance_margin) *balance_margin = bmargin;
   free(front);
   free(x);
   return rounds;
+}
+
+int32_t oracle_push_continue(int32_t n, const int32_t *rowptr,
+                             const int32_t *colidx, double alpha, double rmax,
+                             double *r, double *q, int32_t max_rounds,
+                             int32_t *round_sizes, int64_t *edge_ops,
+                             int32_t *frontier_log, int64_t frontier_cap,
+                             double *min_margin) {
+  return push_core(n, rowptr, colidx, alpha, rmax, r, q, max_rounds, round_sizes,
+                   edge_ops, frontier_log, frontier_cap, min_margin, 0.0, -1.0, NULL,
+                   NULL);
+}
+
+/* Algorithm 3's push: Algorithm 1 from r = e_s with the balance rule. */
+int32_t oracle_push_balanced(int32_t n, const int32_t *rowptr, const int32_t *colidx,
+                             int32_t s, double alpha, double rmax, double omega_unit,
+                             double walk_cost, double *r, double *q, int32_t max_rounds,
+                             int32_t *round_sizes, int64_t *edge_ops,
+                             int32_t *frontier_log, int64_t frontier_cap,
+                             double *min_margin, double *balance_margin,
+                             int32_t *stopped) {
+  for (int32_t v = 0; v < n; ++v) { r[v] = 0.0; q[v] = 0.0; }
+  r[s] = 1.0;
+  return push_core(n, rowptr, colidx, alpha, rmax, r, q, max_rounds, round_sizes,
+                   edge_ops, frontier_log, frontier_cap, min_margin, omega_unit,
+                   walk_cost, balance_margin, stopped);
 }
 
 /* Algorithm 1 from r = e_s, q = 0. */
@@ -223,10 +272,13 @@ int64_t oracle_plan(int32_t n, const double *r, double omega_unit,
 /* a_i r_sum / omega). steps counts moves. If endpoints is given it receives */
 /* the end point of every walk in plan order.                                */
 /* ------------------------------------------------------------------------ */
+/* With first_move set (Algorithm 3, zero-hop walks pruned) the step-0     */
+/* block only chooses the first out-neighbour (no stop test), so every walk */
+/* starts at a random out-neighbour of v; later steps are as above.         */
 void oracle_walks(int32_t n, const int32_t *rowptr, const int32_t *colidx,
                   uint32_t source, uint32_t seed, uint32_t t_alpha,
                   int64_t entries, const int32_t *pv, const uint64_t *pomega,
-                  const double *pw, uint64_t *cnt, double *acc,
+                  const double *pw, int32_t first_move, uint64_t *cnt, double *acc,
                   uint64_t *steps, int32_t *endpoints) {
   (void)n;
   const uint32_t key[2] = {source, seed};
@@ -240,7 +292,7 @@ void oracle_walks(int32_t n, const int32_t *rowptr, const int32_t *colidx,
         uint32_t ctr[4] = {(uint32_t)v, (uint32_t)j, b, 0u};
         uint32_t y[4];
         oracle_philox4x32_10(ctr, key, y);
-        if (y[0] < t_alpha) break;
+        if (!(first_move && b == 0) && y[0] < t_alpha) break;
         uint64_t d = (uint64_t)(rowptr[x + 1] - rowptr[x]);
         uint64_t U = ((uint64_t)y[1] << 32) | (uint64_t)y[2];
         uint64_t idx = (uint64_t)(((unsigned __int128)U * d) >> 64);
