@@ -81,6 +81,7 @@ def main():
     ap.add_argument("--sources", type=int, default=0,
                     help="use only the workload's first N sources (0: all)")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
+    ap.add_argument("--no-alg3", action="store_true", help="skip the Algorithm 3 leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy, whose HBM counter "
                          "readings calibrate FETCH_SIZE / WRITE_SIZE")
@@ -211,6 +212,37 @@ def main():
                                 "timed step; the eps guarantee holds for any r_max (Lemma 2)")
         log(f"batched + learned r_max: {B * args.steps / dtl:.1f} q/s")
 
+    alg3 = None
+    if not args.no_alg3:
+        # Algorithm 3 (zero-hop pruning + push/walk balance): one walk's cost in
+        # residue increments from this run's own phase timers, r_max floor
+        # r_max* / 32 so that the balance rule ends the push
+        push_unit = ph["ms_push"] / max(1, sum(s["edge_ops"] for s in stats0))
+        walk_unit = ph["ms_walk"] / max(1, sum(s["walks"] for s in stats0))
+        wc = walk_unit / push_unit
+        rstar = stats0[0]["rmax"]
+        q3 = [fora.make_queries(srcs[a:b], alpha=alpha, eps=eps, k=k, seed=seed, n=g.n,
+                                rmax=rstar / 32, flags=fora.FORA_PRUNE_ZERO_HOP |
+                                fora.FORA_BALANCE, walk_cost=wc) for a, b in waves]
+        for _ in range(args.warmup):
+            run_all(queries=q3)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        a_steps = 0
+        for _ in range(args.steps):
+            pw3 = run_all(stats=True, queries=q3)
+            a_steps += sum(x["steps"] for w in pw3 for x in w)
+        torch.cuda.synchronize()
+        dt3 = time.perf_counter() - t3
+        st3 = [x for w in pw3 for x in w]
+        alg3 = dict(queries_per_s=round(B * args.steps / dt3, 2), walk_steps_per_s=a_steps / dt3,
+                    ms_per_step=round(dt3 / args.steps * 1e3, 3), walk_cost=round(wc, 3),
+                    rmax_floor="r_max*/32",
+                    balance_stopped=sum(x["balance_stopped"] for x in st3),
+                    edge_ops=sum(x["edge_ops"] for x in st3),
+                    walks=sum(x["walks"] for x in st3))
+        log(f"Algorithm 3 (pruned + balanced, walk_cost {wc:.2f}): {alg3['queries_per_s']} q/s")
+
     graph_mode = None
     if graph_rounds > 0 and not args.no_graph:
         G.set_tuning(graph_rounds=graph_rounds)
@@ -264,6 +296,7 @@ def main():
         "queries_per_s": round(qps, 2),
         "plain_single_query": single,
         "batched_learned_rmax": learned_leg,
+        "batched_alg3": alg3,
         "graph_replay": graph_mode,
         "tuning": tuning,
         "phases_ms": {p: round(float(v), 3) for p, v in ph.items()},

@@ -64,6 +64,9 @@ typedef struct fora_stats {
   float ms_walk;           /*  in every entry); ms_walk spans exactly the walk */
   float ms_topk;           /*  kernel launch                                   */
   uint32_t pull_rounds;    /* push rounds that ran as a pull over in-edges     */
+  uint32_t balance_stopped; /* FORA_BALANCE: the rule held at the last round
+                               boundary (it ended the push, or the push ended
+                               there by itself)                                 */
 } fora_stats;
 
 /* One query of a batch. */
@@ -76,7 +79,23 @@ typedef struct fora_query {
   double pf;     /* 0 < pf < 1                                               */
   double rmax;   /* > 0: use this r_max; <= 0: eqn:rmax (section 3.2)        */
   uint64_t seed; /* low 32 bits form the second Philox key word              */
+  uint32_t flags;    /* 0 (Algorithm 2) or FORA_PRUNE_ZERO_HOP | FORA_BALANCE */
+  uint32_t reserved; /* 0                                                     */
+  double walk_cost;  /* FORA_BALANCE: cost of one walk in residue increments */
 } fora_query;
+
+/* Algorithm 3 (section 5), per query:
+ * FORA_PRUNE_ZERO_HOP (section 5.1): pi_hat starts at q + alpha r; from each
+ *   v with residue, omega_v = ceil(r'(v) omega_unit) walks with
+ *   r' = (1 - alpha) r (FP64 from the FP32 residue), each starting with a
+ *   forced move (the step-0 Philox block only picks the out-neighbour) and
+ *   adding r'(v) / omega_v at its end point.
+ * FORA_BALANCE (section 5.2): before each push round the push stops once its
+ *   residue increments so far reach the estimated walk cost
+ *   (1 - alpha * pushed mass) (1 - alpha) omega_unit walk_cost; r_max still
+ *   bounds the push from below. */
+#define FORA_PRUNE_ZERO_HOP 1u
+#define FORA_BALANCE 2u
 
 #define FORA_MAX_K 4096
 #define FORA_MAX_BATCH 4096

@@ -133,7 +133,8 @@ void oracle_constants(int64_t m, double alpha, double eps, double delta,
 /* FC >= r_sum (1 - alpha) omega_unit walk_cost, the estimated cost of the  */
 /* walks in edge-operation units. *balance_margin (if given) receives the   */
 /* smallest |FC - estimate| / estimate over the tests made; *stopped is 1   */
-/* if the rule ended the push.                                              */
+/* if the rule held at the last boundary tested (it ended the push, or the  */
+/* push ended there by itself).                                             */
 static int32_t push_core(int32_t n, const int32_t *rowptr, const int32_t *colidx,
                          double alpha, double rmax, double *r, double *q,
                          int32_t max_rounds, int32_t *round_sizes,
@@ -159,8 +160,8 @@ static int32_t push_core(int32_t n, const int32_t *rowptr, const int32_t *colidx
       }
       if (r[v] > thr) front[nf++] = v;
     }
-    if (nf == 0) break;
     if (walk_cost >= 0.0) {
+      /* tested at every round boundary, the last one included */
       const double r_sum = 1.0 - alpha * pushed;
       const double est = r_sum * (1.0 - alpha) * omega_unit * walk_cost;
       if (est > 0.0) {
@@ -172,6 +173,7 @@ static int32_t push_core(int32_t n, const int32_t *rowptr, const int32_t *colidx
         break;
       }
     }
+    if (nf == 0) break;
     if (rounds == max_rounds) { rounds = -1; break; }
     if (round_sizes) round_sizes[rounds] = nf;
     if (frontier_log) {

@@ -92,6 +92,10 @@ int check_query(const fora_graph* g, const fora_query& q) {
   if (!(q.pf > 0.0 && q.pf < 1.0)) return fail(FORA_E_ARG, "pf must be in (0,1)");
   if (q.k < 1 || q.k > n || q.k > FORA_MAX_K) return fail(FORA_E_ARG, "k must be in [1, min(n, FORA_MAX_K)]");
   if (!(q.rmax <= 0.0 || std::isfinite(q.rmax))) return fail(FORA_E_ARG, "rmax must be finite");
+  if ((q.flags & ~(FORA_PRUNE_ZERO_HOP | FORA_BALANCE)) != 0 || q.reserved != 0)
+    return fail(FORA_E_ARG, "unknown query flags");
+  if ((q.flags & FORA_BALANCE) && !(q.walk_cost >= 0.0 && std::isfinite(q.walk_cost)))
+    return fail(FORA_E_ARG, "walk_cost must be finite and >= 0");
   return FORA_OK;
 }
 
@@ -115,6 +119,8 @@ QueryDev plan_query(const fora_graph* g, const fora_query& q) {
   d.key0 = (uint32_t)q.src;
   d.key1 = (uint32_t)(q.seed & 0xFFFFFFFFull);
   d.t_alpha = (uint32_t)std::floor(std::ldexp(q.alpha, 32));
+  d.flags = q.flags;
+  d.walk_cost = (q.flags & FORA_BALANCE) ? q.walk_cost : 0.0;
   return d;
 }
 
@@ -233,6 +239,7 @@ int finish(fora_graph* g, const Call& c, int batch, hipStream_t s, fora_stats* h
         o.steps += q.steps;
         o.r_sum += q.r_sum;
         o.pull_rounds += (uint32_t)q.pull_rounds;
+        o.balance_stopped |= (uint32_t)(q.balance_stopped != 0);
       }
       o.rmax = qd[b].rmax;
       o.omega_unit = qd[b].omega_unit;
@@ -401,6 +408,7 @@ Layout make_layout(const GraphDev& g, int32_t batch) {
   L.cand_cnt = take(4 * (size_t)batch);
   L.incd = take(4 * cap);
   L.ecnt = take(8 * 2 * (size_t)kStatSlots * batch);
+  L.stop = take(4 * (size_t)batch);
   L.zero_end = align_up(off, 256);
   L.mode = take(4 * (size_t)batch);
   L.pull_list = take(4 * (size_t)batch);
@@ -447,6 +455,7 @@ Ws carve(const Layout& L, void* base) {
   w.ecnt = (u64*)(p + L.ecnt);
   w.mode = (int32_t*)(p + L.mode);
   w.pull_list = (int32_t*)(p + L.pull_list);
+  w.stop = (int32_t*)(p + L.stop);
   w.plan_gi = (u64*)(p + L.plan_gi);
   w.plan_off = (u64*)(p + L.plan_off);
   w.plan_wfx = (u64*)(p + L.plan_wfx);
@@ -955,6 +964,8 @@ int fora_push_sweep(const fora_graph* gc, int32_t batch, const fora_query* h_que
   for (int b = 0; b < batch; ++b) {
     fora_query q = h_queries[b];
     q.rmax = 0.0;
+    q.flags = 0;  // the sweep measures Algorithm 1 and 2 as they stand
+    q.walk_cost = 0.0;
     rc = check_query(g, q);
     if (rc != FORA_OK) return rc;
     base[b] = plan_query(g, q);

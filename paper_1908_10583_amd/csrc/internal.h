@@ -56,10 +56,11 @@ struct QueryDev {
   int32_t k;
   uint32_t key0, key1;  // Philox key: (source, seed)
   uint32_t t_alpha;     // stop iff first Philox word < t_alpha
-  uint32_t pad;
+  uint32_t flags;       // FORA_PRUNE_ZERO_HOP | FORA_BALANCE
   double alpha;
   double rmax;
   double omega_unit;
+  double walk_cost;     // FORA_BALANCE: one walk's cost in residue increments
 };
 
 // Per-query counters, each query's spread over kStatSlots slots so that
@@ -74,6 +75,8 @@ struct StatSlot {
   int32_t rounds;
   int32_t term_violations;
   u64 pull_rounds;
+  double mass;           // residue pushed (sum of x), FORA_BALANCE queries only
+  u64 balance_stopped;   // set in slot 0 by the round-boundary test
 };
 typedef StatSlot QueryStatsDev;
 
@@ -119,7 +122,7 @@ struct GraphDev {
 
 struct Layout {
   size_t ctrl, qstats, queries, r, q, cnt, acc, pi;
-  size_t fr0, fr1, frx, hub_idx, hub_base, incd, ecnt, mode, pull_list;
+  size_t fr0, fr1, frx, hub_idx, hub_base, incd, ecnt, mode, pull_list, stop;
   size_t plan_gi, plan_off, plan_wfx;
   size_t tile_cnt, tile_walks, tile_eoff, tile_woff;
   size_t hist, sel, cand_key, cand_id, cand_cnt, blk_ties;
@@ -147,6 +150,7 @@ struct Ws {
   u64* ecnt;      // [2][batch][kStatSlots]: frontier edges per query, by round parity
   int32_t* mode;  // [batch]: 1 if the query's current round pulls
   int32_t* pull_list;  // queries in pull mode this round
+  int32_t* stop;       // [batch]: 0, or 1 + the first round the balance rule skips
   u64* plan_gi;
   u64* plan_off;
   u64* plan_wfx;

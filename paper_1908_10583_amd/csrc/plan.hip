@@ -3,7 +3,8 @@
 //   omega_v = ceil(r(v) * omega_unit)          (FP64 from the FP32 residue)
 //   weight  = round(r(v) / omega_v * 2^62)     (unsigned fixed point)
 // and an exclusive scan of omega_v over (b, v) in row-major order gives every
-// walk a global id. Also collects r_sum per query and counts residues left
+// walk a global id. With FORA_PRUNE_ZERO_HOP (Algorithm 3) the walks carry
+// r'(v) = (1 - alpha) r(v) instead (FP64 from the FP32 residue). Also collects r_sum per query and counts residues left
 // above r_max * d(v) (must be zero after the push).
 #include "internal.h"
 #include "scan.h"
@@ -33,6 +34,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_count(
   __syncthreads();
   const double wu = Q[b].omega_unit;
   const double rmax = Q[b].rmax;
+  const double scale = (Q[b].flags & FORA_PRUNE_ZERO_HOP) ? 1.0 - Q[b].alpha : 1.0;
   u64 c = 0, walks = 0, viol = 0;
   double rs = 0.0;
   bool ovf = false;
@@ -41,7 +43,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_count(
     const int lv = threadIdx.x * kPlanPerThread + k;
     const float rv = s_r[lv];
     if (rv > 0.0f) {
-      const double om = ceil((double)rv * wu);
+      const double om = ceil((scale == 1.0 ? (double)rv : scale * (double)rv) * wu);
       ovf |= om >= 4294967296.0;
       ++c;
       walks += (u64)om;
@@ -121,12 +123,13 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_write(
   __syncthreads();
   const size_t tile = (size_t)b * tiles_per_row + blockIdx.x;
   const double wu = Q[b].omega_unit;
+  const double scale = (Q[b].flags & FORA_PRUNE_ZERO_HOP) ? 1.0 - Q[b].alpha : 1.0;
   u64 c = 0, walks = 0;
   double om[kPlanPerThread];
 #pragma unroll
   for (int k = 0; k < kPlanPerThread; ++k) {
     const float rv = s_r[threadIdx.x * kPlanPerThread + k];
-    om[k] = rv > 0.0f ? ceil((double)rv * wu) : 0.0;
+    om[k] = rv > 0.0f ? ceil((scale == 1.0 ? (double)rv : scale * (double)rv) * wu) : 0.0;
     c += rv > 0.0f ? 1 : 0;
     walks += (u64)om[k];
   }
@@ -140,7 +143,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_write(
     if (rv > 0.0f) {
       plan_gi[e] = ((u64)b << 32) | (uint32_t)(v0 + lv);
       plan_off[e] = woff;
-      plan_wfx[e] = __double2ull_rn(((double)rv / om[k]) * kFx);
+      const double rw = scale == 1.0 ? (double)rv : scale * (double)rv;
+      plan_wfx[e] = __double2ull_rn((rw / om[k]) * kFx);
       ++e;
       woff += (u64)om[k];
     }

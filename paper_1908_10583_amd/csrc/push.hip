@@ -31,12 +31,23 @@ namespace fora {
 constexpr int kScatterBlock = 256;
 constexpr unsigned kQueueCap = 1024;  // LDS-staged next-frontier entries per block
 
+// FORA_BALANCE before round 0 (nothing pushed): stop at once iff the
+// estimated walk cost (1 - alpha) omega_unit walk_cost is not positive.
+__device__ __forceinline__ bool balance_met(const QueryDev& q, u64 edge_ops, double mass) {
+  const double est = (1.0 - q.alpha * mass) * (1.0 - q.alpha) * q.omega_unit * q.walk_cost;
+  return (double)edge_ops >= est;
+}
+
 __global__ void k_init_queries(const QueryDev* Q, int batch, int n, const int2* info, float* r,
-                               u64* fr0, Ctrl* ctrl) {
+                               u64* fr0, Ctrl* ctrl, int32_t* stop, StatSlot* slots) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
   const int s = Q[b].src;
   r[(size_t)b * n + s] = 1.0f;
+  if ((Q[b].flags & FORA_BALANCE) && balance_met(Q[b], 0, 0.0)) {
+    stop[b] = 1;
+    slots[(size_t)b * kStatSlots].balance_stopped = 1;
+  }
   if (1.0 > Q[b].rmax * (double)info[s].y) {
     const u64 pos = atomicAdd(&ctrl->fr_cnt[0], 1ull);
     fr0[pos] = ((u64)b << 32) | (uint32_t)s;
@@ -45,7 +56,7 @@ __global__ void k_init_queries(const QueryDev* Q, int batch, int n, const int2* 
 
 hipError_t launch_init_queries(const GraphDev& g, const Ws& w, int batch, hipStream_t s) {
   k_init_queries<<<(batch + 255) / 256, 256, 0, s>>>(w.queries, batch, g.n, g.info, w.r,
-                                                     w.fr[0], w.ctrl);
+                                                     w.fr[0], w.ctrl, w.stop, w.qstats);
   return hipGetLastError();
 }
 
@@ -55,8 +66,8 @@ __global__ __launch_bounds__(256) void k_push_snapshot(
     int t, Ctrl* ctrl, const u64* __restrict__ fr_in, float* __restrict__ frx,
     float* __restrict__ r, float* __restrict__ q, float* __restrict__ incd,
     const QueryDev* __restrict__ Q, StatSlot* slots, u64* ecnt, const int2* __restrict__ info,
-    const int32_t* __restrict__ rank, int n, int batch, int32_t* frontier_log, int64_t log_cap,
-    u64 cap, u64* hub_idx,
+    const int32_t* __restrict__ rank, const int32_t* __restrict__ stop, int n, int batch,
+    int32_t* frontier_log, int64_t log_cap, u64 cap, u64* hub_idx,
     u64* hub_base, u64 hub_cap) {
   extern __shared__ unsigned char smem[];
   u64* s_edges = (u64*)smem;
@@ -78,9 +89,12 @@ __global__ __launch_bounds__(256) void k_push_snapshot(
     const u64 e = fr_in[i];
     const int b = (int)(e >> 32);
     const int v = (int)(uint32_t)e;
+    if (stop[b] != 0 && t + 1 >= stop[b]) continue;  // the balance rule ended this push
     const size_t gi = (size_t)b * n + v;
     const float x = r[gi];
     r[gi] = 0.0f;
+    if (Q[b].flags & FORA_BALANCE)
+      atomicAdd(&slots[(size_t)b * kStatSlots + (blockIdx.x & (kStatSlots - 1))].mass, (double)x);
     const double alpha = Q[b].alpha;
     q[gi] = (float)((double)q[gi] + alpha * (double)x);
     const int d = info[v].y;
@@ -124,7 +138,9 @@ __global__ __launch_bounds__(256) void k_push_snapshot(
 // queries; clear the next round's frontier-edge slots.
 __global__ __launch_bounds__(256) void k_push_mode(int t, Ctrl* ctrl, u64* ecnt, int32_t* mode,
                                                    int32_t* pull_list, StatSlot* slots,
-                                                   int batch, u64 n_plus_m, int pull_ratio) {
+                                                   const QueryDev* __restrict__ Q,
+                                                   int32_t* stop, int batch, u64 n_plus_m,
+                                                   int pull_ratio) {
   __shared__ int32_t s_tmp[4];
   const u64* ec = ecnt + (size_t)(t & 1) * batch * kStatSlots;
   u64* ec_next = ecnt + (size_t)((t + 1) & 1) * batch * kStatSlots;
@@ -138,6 +154,19 @@ __global__ __launch_bounds__(256) void k_push_mode(int t, Ctrl* ctrl, u64* ecnt,
       pull = (pull_ratio > 0 && edges > 0 && edges * (u64)pull_ratio > n_plus_m) ? 1 : 0;
       mode[b] = pull;
       if (pull) slots[(size_t)b * kStatSlots].pull_rounds += 1;
+      // FORA_BALANCE: the test before round t+1, over everything pushed so far
+      if ((Q[b].flags & FORA_BALANCE) && stop[b] == 0) {
+        u64 fc = 0;
+        double mass = 0.0;
+        for (int k = 0; k < kStatSlots; ++k) {
+          fc += slots[(size_t)b * kStatSlots + k].edge_ops;
+          mass += slots[(size_t)b * kStatSlots + k].mass;
+        }
+        if (balance_met(Q[b], fc, mass)) {
+          stop[b] = t + 2;
+          slots[(size_t)b * kStatSlots].balance_stopped = 1;
+        }
+      }
     }
     int32_t tot;
     const int32_t pos = carry + block_exclusive_scan(pull, s_tmp, tot);
@@ -300,9 +329,10 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
 __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
     int t, Ctrl* ctrl, const u64* __restrict__ fr_in, const float* __restrict__ frx,
     u64* __restrict__ fr_out, u64 cap, float* __restrict__ r, float* __restrict__ incd,
-    const int32_t* __restrict__ mode, const QueryDev* __restrict__ Q,
-    const int2* __restrict__ info, const int32_t* __restrict__ colidx,
-    const int32_t* __restrict__ rank, int n, const u64* __restrict__ hub_idx,
+    const int32_t* __restrict__ mode, const int32_t* __restrict__ stop,
+    const QueryDev* __restrict__ Q, const int2* __restrict__ info,
+    const int32_t* __restrict__ colidx, const int32_t* __restrict__ rank, int n,
+    const u64* __restrict__ hub_idx,
     const u64* __restrict__ hub_base, u64 hub_cap) {
   __shared__ u64 s_pre[kScatterBlock];
   __shared__ int32_t s_start[kScatterBlock];
@@ -377,7 +407,8 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
       s_ent_b[threadIdx.x] = (uint32_t)b;
       s_inc[threadIdx.x] = frx[i];
       s_rmax[threadIdx.x] = Q[b].rmax;
-      deg = (inf.y > kHubDeg || mode[b]) ? 0ull : (u64)inf.y;
+      const bool skip = mode[b] || (stop[b] != 0 && t + 1 >= stop[b]);
+      deg = (inf.y > kHubDeg || skip) ? 0ull : (u64)inf.y;
     }
     u64 total;
     const u64 pre = block_exclusive_scan(deg, s_tmp, total);
@@ -446,19 +477,20 @@ hipError_t launch_push_round(const GraphDev& g, const Ws& w, const Layout& L, in
   const size_t smem = (size_t)batch * (sizeof(u64) + sizeof(uint32_t));
   const u64 cap = (u64)L.cap;
   k_push_snapshot<<<blocks, 256, smem, s>>>(t, w.ctrl, w.fr[par], w.frx, w.r, w.q, w.incd,
-                                            w.queries, w.qstats, w.ecnt, g.info, g.rank, g.n,
-                                            batch,
+                                            w.queries, w.qstats, w.ecnt, g.info, g.rank, w.stop,
+                                            g.n, batch,
                                             frontier_log, log_cap, cap, w.hub_idx, w.hub_base,
                                             (u64)L.hub_cap);
-  k_push_mode<<<1, 256, 0, s>>>(t, w.ctrl, w.ecnt, w.mode, w.pull_list, w.qstats, batch,
-                                (u64)g.n + (u64)g.m, pull_ratio);
+  k_push_mode<<<1, 256, 0, s>>>(t, w.ctrl, w.ecnt, w.mode, w.pull_list, w.qstats, w.queries,
+                                w.stop, batch, (u64)g.n + (u64)g.m, pull_ratio);
   k_push_pull<<<blocks, kScatterBlock, 0, s>>>(t, w.ctrl, w.fr[par ^ 1], cap, w.r, w.incd,
                                                w.queries, w.pull_list, g.info, g.in_rowptr,
                                                g.in_colidx, g.inhub_node, g.inhub_base,
                                                g.n_inhubs, g.inhub_pieces, g.n);
   k_push_scatter<<<blocks, kScatterBlock, 0, s>>>(t, w.ctrl, w.fr[par], w.frx, w.fr[par ^ 1],
-                                                  cap, w.r, w.incd, w.mode, w.queries, g.info,
-                                                  g.colidx, g.rank, g.n, w.hub_idx, w.hub_base,
+                                                  cap, w.r, w.incd, w.mode, w.stop, w.queries,
+                                                  g.info, g.colidx, g.rank, g.n, w.hub_idx,
+                                                  w.hub_base,
                                                   (u64)L.hub_cap);
   return hipGetLastError();
 }

@@ -23,7 +23,8 @@ __device__ __forceinline__ bool prefix_ok(uint32_t key, int pass, uint32_t prefi
 }
 
 __global__ __launch_bounds__(kTopkThreads) void k_topk_hist(
-    int pass, const float* __restrict__ q, const u64* __restrict__ acc, float* __restrict__ pi,
+    int pass, const float* __restrict__ q, const u64* __restrict__ acc,
+    const float* __restrict__ r, const QueryDev* __restrict__ Q, float* __restrict__ pi,
     int n, uint32_t* hist, const uint32_t* sel, const Ctrl* ctrl) {
   __shared__ uint32_t s_hist[kHistBins];
   if (ctrl->skip) return;
@@ -33,12 +34,15 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk_hist(
   const uint32_t prefix = pass ? sel[b * 4 + 0] : 0u;
   const size_t row = (size_t)b * n;
   const int v0 = blockIdx.x * kTopkTile;
+  // FORA_PRUNE_ZERO_HOP: the zero-hop walks' share alpha r(v) is added exactly
+  const double zero_hop = (Q[b].flags & FORA_PRUNE_ZERO_HOP) ? Q[b].alpha : 0.0;
   for (int k = threadIdx.x; k < kTopkTile; k += kTopkThreads) {
     const int v = v0 + k;
     if (v >= n) break;
     uint32_t key;
     if (pass == 0) {
-      const double p = (double)q[row + v] + (double)acc[row + v] * (1.0 / kFx);
+      double p = (double)q[row + v] + (double)acc[row + v] * (1.0 / kFx);
+      if (zero_hop != 0.0) p += zero_hop * (double)r[row + v];
       const float pf = (float)p;
       pi[row + v] = pf;
       key = __float_as_uint(pf);
@@ -249,8 +253,8 @@ hipError_t launch_topk(const GraphDev& g, const Ws& w, const Layout& L, int batc
                        int32_t* d_ids, float* d_vals, hipStream_t s) {
   dim3 grid((unsigned)L.topk_blocks, (unsigned)batch);
   for (int pass = 0; pass < 3; ++pass) {
-    k_topk_hist<<<grid, kTopkThreads, 0, s>>>(pass, w.q, w.acc, w.pi, g.n, w.hist, w.sel,
-                                              w.ctrl);
+    k_topk_hist<<<grid, kTopkThreads, 0, s>>>(pass, w.q, w.acc, w.r, w.queries, w.pi, g.n,
+                                              w.hist, w.sel, w.ctrl);
     k_topk_select<<<batch, kTopkThreads, 0, s>>>(pass, w.hist, w.sel, w.queries, w.cand_cnt,
                                                  w.ctrl);
   }

@@ -7,6 +7,8 @@
 // below floor(alpha * 2^32); otherwise it moves to out-neighbour
 // floor(U * d(x) / 2^64) of x, where U = word1 * 2^32 + word2. At its end
 // point t it adds 1 to cnt[t] and its entry's fixed-point weight to acc[t].
+// With FORA_PRUNE_ZERO_HOP (Algorithm 3) the step-0 block only chooses the
+// first move: every walk starts at a random out-neighbour of v.
 //
 // With AGG, a wave first adds its end points to a wave-private LDS table
 // keyed by (query, node) and moves the table's sums to HBM when it holds
@@ -134,6 +136,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
   uint32_t v = 0, j = 0, step = 0, k0 = 0, k1 = 0, ta = 0;
   int32_t x = 0;
   uint32_t q = 0, deg = 1;  // record start and out-degree of x
+  bool forced = false;      // FORA_PRUNE_ZERO_HOP: the next step must move
   u64 wfx = 0;
   int stat_b = -1;
   u64 stat_steps = 0;
@@ -189,6 +192,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
           k0 = Q[b].key0;
           k1 = Q[b].key1;
           ta = Q[b].t_alpha;
+          forced = (Q[b].flags & FORA_PRUNE_ZERO_HOP) != 0;
           active = true;
         }
         cursor += nassign;
@@ -217,7 +221,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
     bool fresh = false;
     if (active) {
       const uint4 y = philox4x32_10(make_uint4(v, j, step, 0u), k0, k1);
-      if (y.x < ta) {
+      if (!forced && y.x < ta) {
         const size_t t = (size_t)b * n + x;
         if (!AGG || !agg_add(agg, (u64)t, wfx, &fresh)) {
           atomicAdd(&cnt[t], 1ull);
@@ -239,6 +243,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
         deg = h.x;
         x = (int32_t)h.y;
         ++step;
+        forced = false;
       }
     }
     if (AGG) agg_fill += (unsigned)__popcll(__ballot(fresh));

@@ -36,7 +36,8 @@ class fora_stats(ctypes.Structure):
                 ("rmax", ctypes.c_double), ("omega_unit", ctypes.c_double),
                 ("t_alpha", ctypes.c_uint32), ("ms_push", ctypes.c_float),
                 ("ms_plan", ctypes.c_float), ("ms_walk", ctypes.c_float),
-                ("ms_topk", ctypes.c_float), ("pull_rounds", ctypes.c_uint32)]
+                ("ms_topk", ctypes.c_float), ("pull_rounds", ctypes.c_uint32),
+                ("balance_stopped", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -45,7 +46,9 @@ class fora_stats(ctypes.Structure):
 class fora_query(ctypes.Structure):
     _fields_ = [("src", ctypes.c_int32), ("k", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("eps", ctypes.c_double), ("delta", ctypes.c_double), ("pf", ctypes.c_double),
-                ("rmax", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("rmax", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("walk_cost", ctypes.c_double)]
 
 
 class fora_tuning(ctypes.Structure):
@@ -118,6 +121,8 @@ EXPORTED = ["fora_last_error", "fora_build_csr", "fora_free_graph", "fora_graph_
             "fora_mlp_forward", "fora_mlp_backward", "fora_adam_step", "fora_mlp_to_bf16",
             "fora_mlp_forward_bf16", "fora_predict_rmax", "fora_push_sweep"]
 
+FORA_PRUNE_ZERO_HOP = 1
+FORA_BALANCE = 2
 FORA_MLP_FEATURES = 7
 FORA_MLP_PARAMS = 4751
 FORA_MLP_ACTS = 128
@@ -257,8 +262,10 @@ def fora_ssppr(g: Graph, src: int, alpha: float = 0.2, eps: float = 0.5,
 
 
 def make_queries(srcs, alpha=0.2, eps=0.5, delta=None, pf=None, k=500, rmax=None, seed=0,
-                 n: int | None = None):
-    """An array of ``fora_query`` (scalars broadcast; lists give per-query values)."""
+                 n: int | None = None, flags=0, walk_cost=0.0):
+    """An array of ``fora_query`` (scalars broadcast; lists give per-query values).
+    flags: FORA_PRUNE_ZERO_HOP | FORA_BALANCE (Algorithm 3); walk_cost: one
+    walk's cost in residue increments for FORA_BALANCE."""
     srcs = list(np.asarray(srcs).reshape(-1))
     B = len(srcs)
 
@@ -274,9 +281,11 @@ def make_queries(srcs, alpha=0.2, eps=0.5, delta=None, pf=None, k=500, rmax=None
     delta = per(delta, None if n is None else 1.0 / n)
     pf = per(pf, None if n is None else 1.0 / n)
     arr = (fora_query * B)()
-    for i, (s, a, e, d, p, kk, r, sd) in enumerate(zip(srcs, per(alpha), per(eps), delta, pf,
-                                                       per(k), per(rmax, 0.0), per(seed))):
+    for i, (s, a, e, d, p, kk, r, sd, fl, wc) in enumerate(
+            zip(srcs, per(alpha), per(eps), delta, pf, per(k), per(rmax, 0.0), per(seed),
+                per(flags), per(walk_cost))):
         arr[i].src, arr[i].k = int(s), int(kk)
+        arr[i].flags, arr[i].walk_cost = int(fl), float(wc)
         arr[i].alpha, arr[i].eps = float(a), float(e)
         arr[i].delta, arr[i].pf = float(d), float(p)
         arr[i].rmax = 0.0 if r is None else float(r)
