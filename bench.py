@@ -35,12 +35,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def recorded_traffic(kernel: str):
-    """HBM-side bytes per launch from the committed counter record, or None if
-    the kernel's sources changed since the counters were taken."""
+def recorded_traffic(kernel: str, tag: str):
+    """HBM-side bytes per launch from the committed counter record for this
+    workload (tag: workload and batch, e.g. rmat20_b100), or None if there is
+    none or the kernel's sources changed since the counters were taken."""
     import glob
     import hashlib
-    for path in glob.glob(os.path.join(ROOT, "profiles", f"{kernel}_*_traffic.json")):
+    for path in glob.glob(os.path.join(ROOT, "profiles", f"{kernel}_{tag}_traffic.json")):
         rec = json.load(open(path))
         h = hashlib.sha256()
         try:
@@ -173,7 +174,7 @@ def main():
     walk_s = float(np.mean(walk_ms)) / 1e3
     alg_bytes = BYTES_PER_STEP * per_launch_steps + BYTES_PER_WALK * per_launch_walks
     achieved = alg_bytes / walk_s / 1e9
-    traffic, traffic_src = recorded_traffic("k_walks")
+    traffic, traffic_src = recorded_traffic("k_walks", f"{args.workload}_b{WB}")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS,
                     unit="GB/s", frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
                     traffic_source=traffic_src, kernel="k_walks", bytes_per_launch=alg_bytes,
