@@ -277,3 +277,39 @@ def fora(g, s: int, alpha: float = 0.2, eps: float = 0.5, delta: float | None = 
     out.update(ps)
     out.update(wk)
     return out
+
+def topk_deltas(n: int, k: int):
+    """Algorithm 5's thresholds: delta = 1/k, 1/(2k), ... while above 1/n,
+    then 1/n (the last iteration returns whatever it finds)."""
+    out = []
+    d = 1.0 / k
+    while d > 1.0 / n:
+        out.append(d)
+        d /= 2.0
+    out.append(1.0 / n)
+    return out
+
+
+def fora_topk(g, s: int, k: int, alpha: float = 0.2, eps: float = 0.5, pf: float | None = None,
+              seed: int = 0, prune: bool = False) -> dict:
+    """Top-k FORA (Algorithm 5): for delta = 1/k, 1/(2k), ..., 1/n run
+    Algorithm 2 with eps' = eps / 2, p_f' = p_f / (n log2(n / k)) and r_max by
+    eqn:rmax for those parameters (iteration i uses Philox seed seed + i);
+    stop at the first iteration whose k-th largest estimate (rounded to FP32,
+    the precision the result is returned in) is at least (1 + eps) delta."""
+    n = g.n
+    pf = 1.0 / n if pf is None else pf
+    pf_it = pf / (n * max(math.log2(n / k), 1.0))
+    trace = []
+    out = None
+    deltas = topk_deltas(n, k)
+    for i, d in enumerate(deltas):
+        out = fora(g, s, alpha=alpha, eps=eps / 2, delta=d, pf=pf_it, k=k, seed=seed + i,
+                   prune=prune)
+        kth = float(np.float32(out["topk_vals"][k - 1]))
+        trace.append(dict(delta=d, kth=kth, bound=(1 + eps) * d))
+        if kth >= (1 + eps) * d or i == len(deltas) - 1:
+            break
+    out = dict(out)
+    out.update(iterations=len(trace), delta=trace[-1]["delta"], trace=trace, pf_iter=pf_it)
+    return out
