@@ -194,6 +194,25 @@ int fora_ssppr_batch(const fora_graph *g, int32_t batch,
 
 /* ---- step-level entry points (used to compare each phase on its own) ---- */
 
+/* ---- top-k FORA (Algorithm 5, section 6.2) ------------------------------
+ * For each query, with its own k: run Algorithm 2 with eps' = eps / 2,
+ * p_f' = p_f / (n max(log2(n / k), 1)) and delta = 1/k, 1/(2k), ... (while
+ * above 1/n, then 1/n), r_max by eqn:rmax for those parameters unless the
+ * query's rmax is set, and Philox seed (seed + iteration); stop at the first
+ * iteration whose k-th largest estimate (FP32) is at least (1 + eps) delta,
+ * or at delta = 1/n. The query's delta field is ignored; flags apply to every
+ * iteration. Queries that stop leave the batch; the rest run the next
+ * iteration together.
+ * Workspace: fora_topk_workspace_size(g, batch, kmax) bytes (the batched
+ * workspace plus staging rows). Outputs as fora_ssppr_batch; h_stats
+ * (nullable) holds each query's last iteration; h_iterations (int32[batch],
+ * nullable) the iterations run; h_delta (double[batch], nullable) the final
+ * delta. Waits for completion. */
+int fora_topk_workspace_size(const fora_graph *g, int32_t batch, int32_t kmax, size_t *bytes);
+int fora_topk_batch(const fora_graph *g, int32_t batch, const fora_query *h_queries,
+                    int32_t kmax, void *d_ws, size_t ws_bytes, int32_t *d_ids, float *d_vals,
+                    fora_stats *h_stats, int32_t *h_iterations, double *h_delta, void *stream);
+
 /* Only the push phase of fora_ssppr for one source (Algorithm 1,
  * synchronous rounds). Results in the workspace views (row 0).
  * h_round_sizes (nullable, max_rounds entries) receives |F_t|; d_frontiers

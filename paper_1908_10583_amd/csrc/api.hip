@@ -769,6 +769,117 @@ int fora_ssppr_batch(const fora_graph* g, int32_t batch, const fora_query* h_que
                      d_vals, h_stats, (hipStream_t)stream);
 }
 
+int fora_topk_workspace_size(const fora_graph* g, int32_t batch, int32_t kmax, size_t* bytes) {
+  if (!g || !bytes) return fail(FORA_E_ARG, "null argument");
+  if (batch < 1 || batch > FORA_MAX_BATCH) return fail(FORA_E_ARG, "batch out of range");
+  if (kmax < 1 || kmax > FORA_MAX_K) return fail(FORA_E_ARG, "kmax out of range");
+  const size_t rows = (size_t)batch * (size_t)kmax;
+  *bytes = align_up(make_layout(g->dev, batch).total, 256) + align_up(rows * 4, 256) * 2 +
+           align_up((size_t)batch * 4, 256) * 4;
+  return FORA_OK;
+}
+
+// Algorithm 5: iterations of Algorithm 2 at halving delta for the queries
+// that have not stopped yet; finished rows move from the staging rows at
+// the end of the workspace to their final places.
+int fora_topk_batch(const fora_graph* gc, int32_t batch, const fora_query* h_queries,
+                    int32_t kmax, void* d_ws, size_t ws_bytes, int32_t* d_ids, float* d_vals,
+                    fora_stats* h_stats, int32_t* h_iterations, double* h_delta, void* stream) {
+  fora_graph* g = const_cast<fora_graph*>(gc);
+  hipStream_t s = (hipStream_t)stream;
+  if (!g || !h_queries || !d_ws || !d_ids || !d_vals) return fail(FORA_E_ARG, "null argument");
+  size_t need = 0;
+  int rc = fora_topk_workspace_size(g, batch, kmax, &need);
+  if (rc != FORA_OK) return rc;
+  if (ws_bytes < need) return fail(FORA_E_NOMEM, "workspace smaller than fora_topk_workspace_size");
+  const int32_t n = g->dev.n;
+  for (int b = 0; b < batch; ++b) {
+    fora_query q = h_queries[b];
+    q.delta = 1.0;  // replaced per iteration
+    rc = check_query(g, q);
+    if (rc != FORA_OK) return rc;
+    if (q.k > kmax) return fail(FORA_E_ARG, "kmax smaller than a query's k");
+  }
+  // staging rows and small index arrays after the batched workspace
+  const size_t rows = (size_t)batch * (size_t)kmax;
+  char* p = (char*)d_ws + align_up(make_layout(g->dev, batch).total, 256);
+  int32_t* st_ids = (int32_t*)p;
+  p += align_up(rows * 4, 256);
+  float* st_vals = (float*)p;
+  p += align_up(rows * 4, 256);
+  int32_t* d_k = (int32_t*)p;
+  p += align_up((size_t)batch * 4, 256);
+  float* d_kth = (float*)p;
+  p += align_up((size_t)batch * 4, 256);
+  int32_t* d_from = (int32_t*)p;
+  p += align_up((size_t)batch * 4, 256);
+  int32_t* d_to = (int32_t*)p;
+  const size_t ws_main = make_layout(g->dev, batch).total;
+
+  std::vector<int32_t> remaining(batch);
+  for (int b = 0; b < batch; ++b) remaining[b] = b;
+  std::vector<fora_query> qv;
+  std::vector<fora_stats> st;
+  std::vector<int32_t> ks, from, to;
+  std::vector<float> kth;
+  std::vector<double> delta_now(batch);
+  for (int it = 0; !remaining.empty(); ++it) {
+    const int B = (int)remaining.size();
+    qv.assign(B, fora_query{});
+    ks.resize(B);
+    std::vector<char> last(B);
+    for (int i = 0; i < B; ++i) {
+      const fora_query& q0 = h_queries[remaining[i]];
+      fora_query q = q0;
+      const double top = 1.0 / (double)q0.k;
+      const double floor_n = 1.0 / (double)n;
+      double d = std::ldexp(top, -it);
+      last[i] = !(d > floor_n);  // the sequence ends with one iteration at 1/n
+      if (last[i]) d = floor_n;
+      q.delta = d;
+      q.eps = q0.eps / 2.0;
+      q.pf = q0.pf / ((double)n * std::max(std::log2((double)n / (double)q0.k), 1.0));
+      q.seed = q0.seed + (uint64_t)it;
+      qv[i] = q;
+      ks[i] = q0.k;
+      delta_now[remaining[i]] = d;
+    }
+    st.assign(B, fora_stats{});
+    rc = run_queries(g, B, qv.data(), kmax, d_ws, ws_main, st_ids, st_vals, st.data(), s);
+    if (rc != FORA_OK) return rc;
+    FORA_HIP(hipMemcpyAsync(d_k, ks.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, s));
+    FORA_HIP(launch_topk_kth(st_vals, kmax, d_k, B, d_kth, s));
+    kth.resize(B);
+    FORA_HIP(hipMemcpyAsync(kth.data(), d_kth, sizeof(float) * B, hipMemcpyDeviceToHost, s));
+    FORA_HIP(hipStreamSynchronize(s));
+    from.clear();
+    to.clear();
+    std::vector<int32_t> next;
+    for (int i = 0; i < B; ++i) {
+      const int b = remaining[i];
+      const double bound = (1.0 + h_queries[b].eps) * delta_now[b];
+      if ((double)kth[i] >= bound || last[i]) {
+        from.push_back(i);
+        to.push_back(b);
+        if (h_stats) h_stats[b] = st[i];
+        if (h_iterations) h_iterations[b] = it + 1;
+        if (h_delta) h_delta[b] = delta_now[b];
+      } else {
+        next.push_back(b);
+      }
+    }
+    if (!from.empty()) {
+      const int c = (int)from.size();
+      FORA_HIP(hipMemcpyAsync(d_from, from.data(), sizeof(int32_t) * c, hipMemcpyHostToDevice, s));
+      FORA_HIP(hipMemcpyAsync(d_to, to.data(), sizeof(int32_t) * c, hipMemcpyHostToDevice, s));
+      FORA_HIP(launch_copy_rows(st_ids, st_vals, kmax, d_from, d_to, c, d_ids, d_vals, s));
+      FORA_HIP(hipStreamSynchronize(s));
+    }
+    remaining.swap(next);
+  }
+  return FORA_OK;
+}
+
 int fora_push_only(const fora_graph* gc, int32_t src, double alpha, double rmax, void* d_ws,
                    size_t ws_bytes, int32_t max_rounds, int32_t* h_round_sizes,
                    int32_t* d_frontiers, int64_t frontier_cap, fora_stats* h_stats,

@@ -213,6 +213,11 @@ hipError_t launch_topk(const GraphDev& g, const Ws& w, const Layout& L, int batc
                        int kmax, int32_t* d_ids, float* d_vals, hipStream_t s);
 hipError_t launch_build_reverse(const GraphDev& g, int32_t* in_rowptr, int32_t* in_colidx,
                                 int32_t* cursor, uint32_t* tsum, hipStream_t s);
+hipError_t launch_topk_kth(const float* vals, int kmax, const int32_t* ks, int count, float* kth,
+                           hipStream_t s);
+hipError_t launch_copy_rows(const int32_t* src_ids, const float* src_vals, int kmax,
+                            const int32_t* from, const int32_t* to, int count, int32_t* dst_ids,
+                            float* dst_vals, hipStream_t s);
 hipError_t launch_build_records(const GraphDev& g, uint32_t* rec_q, uint32_t* rec, int32_t* tmp,
                                 uint32_t* tsum, hipStream_t s);
 // rank[v] from the out-degrees; scratch: 4 int32 arrays of n and sort storage

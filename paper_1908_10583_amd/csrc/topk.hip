@@ -269,4 +269,40 @@ hipError_t launch_topk(const GraphDev& g, const Ws& w, const Layout& L, int batc
   return hipGetLastError();
 }
 
+// Top-k FORA (Algorithm 5) helpers: the k-th value of each staged row, and
+// the copy of finished rows to their final places.
+__global__ void k_topk_kth(const float* __restrict__ vals, int kmax, const int32_t* __restrict__ ks,
+                           int count, float* kth) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) kth[i] = vals[(size_t)i * kmax + ks[i] - 1];
+}
+
+__global__ void k_copy_rows(const int32_t* __restrict__ src_ids, const float* __restrict__ src_vals,
+                            int kmax, const int32_t* __restrict__ from, const int32_t* __restrict__ to,
+                            int count, int32_t* dst_ids, float* dst_vals) {
+  for (int r = blockIdx.x; r < count; r += gridDim.x) {
+    const size_t a = (size_t)from[r] * kmax, b = (size_t)to[r] * kmax;
+    for (int j = threadIdx.x; j < kmax; j += blockDim.x) {
+      dst_ids[b + j] = src_ids[a + j];
+      dst_vals[b + j] = src_vals[a + j];
+    }
+  }
+}
+
+hipError_t launch_topk_kth(const float* vals, int kmax, const int32_t* ks, int count, float* kth,
+                           hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  k_topk_kth<<<(count + 255) / 256, 256, 0, s>>>(vals, kmax, ks, count, kth);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_rows(const int32_t* src_ids, const float* src_vals, int kmax,
+                            const int32_t* from, const int32_t* to, int count, int32_t* dst_ids,
+                            float* dst_vals, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  k_copy_rows<<<count < 1024 ? count : 1024, 256, 0, s>>>(src_ids, src_vals, kmax, from, to, count,
+                                                          dst_ids, dst_vals);
+  return hipGetLastError();
+}
+
 }  // namespace fora

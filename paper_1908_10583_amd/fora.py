@@ -88,6 +88,9 @@ def _load():
                         ctypes.POINTER(fora_stats), P], ctypes.c_int),
         "fora_ssppr_batch": ([P, I32, ctypes.POINTER(fora_query), I32, P, SZ, P, P,
                               ctypes.POINTER(fora_stats), P], ctypes.c_int),
+        "fora_topk_workspace_size": ([P, I32, I32, ctypes.POINTER(SZ)], ctypes.c_int),
+        "fora_topk_batch": ([P, I32, ctypes.POINTER(fora_query), I32, P, SZ, P, P,
+                             ctypes.POINTER(fora_stats), P, P, P], ctypes.c_int),
         "fora_push_only": ([P, I32, F64, F64, P, SZ, I32, P, P, I64,
                             ctypes.POINTER(fora_stats), P], ctypes.c_int),
         "fora_walk_only": ([P, I64, P, P, P, U32, U32, F64, P, SZ, ctypes.POINTER(U64), P],
@@ -119,7 +122,8 @@ EXPORTED = ["fora_last_error", "fora_build_csr", "fora_free_graph", "fora_graph_
             "fora_workspace_size", "fora_workspace_views", "fora_ssppr", "fora_ssppr_batch",
             "fora_push_only", "fora_walk_only", "fora_philox", "fora_features",
             "fora_mlp_forward", "fora_mlp_backward", "fora_adam_step", "fora_mlp_to_bf16",
-            "fora_mlp_forward_bf16", "fora_predict_rmax", "fora_push_sweep"]
+            "fora_mlp_forward_bf16", "fora_predict_rmax", "fora_push_sweep",
+            "fora_topk_workspace_size", "fora_topk_batch"]
 
 FORA_PRUNE_ZERO_HOP = 1
 FORA_BALANCE = 2
@@ -308,6 +312,37 @@ def fora_ssppr_batch(g: Graph, queries, kmax: int | None = None,
     _check(_lib.fora_ssppr_batch(g.handle, B, queries, kmax, _ptr(ws), ws.numel(), _ptr(ids),
                                  _ptr(vals), st, ctypes.c_void_p(_stream(stream))))
     return Result(ids, vals, [s.as_dict() for s in st] if st is not None else None)
+
+
+def fora_topk_workspace_size(g: Graph, batch: int, kmax: int) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.fora_topk_workspace_size(g.handle, batch, kmax, ctypes.byref(out)))
+    return out.value
+
+
+def fora_topk_batch(g: Graph, queries, kmax: int | None = None, ws: torch.Tensor | None = None,
+                    stats: bool = False, out: tuple | None = None, stream=None):
+    """Top-k FORA (Algorithm 5) for every query; returns (Result, iterations,
+    final delta) with the last two as numpy arrays."""
+    B = len(queries)
+    kmax = max(q.k for q in queries) if kmax is None else kmax
+    if ws is None:
+        ws = torch.empty(fora_topk_workspace_size(g, B, kmax), dtype=torch.uint8,
+                         device=g.device)
+    if out is None:
+        ids = torch.empty((B, kmax), dtype=torch.int32, device=g.device)
+        vals = torch.empty((B, kmax), dtype=torch.float32, device=g.device)
+    else:
+        ids, vals = out
+    st = (fora_stats * B)() if stats else None
+    iters = np.zeros(B, np.int32)
+    delta = np.zeros(B, np.float64)
+    _check(_lib.fora_topk_batch(g.handle, B, queries, kmax, _ptr(ws), ws.numel(), _ptr(ids),
+                                _ptr(vals), st, iters.ctypes.data_as(ctypes.c_void_p),
+                                delta.ctypes.data_as(ctypes.c_void_p),
+                                ctypes.c_void_p(_stream(stream))))
+    return (Result(ids, vals, [s.as_dict() for s in st] if st is not None else None), iters,
+            delta)
 
 
 def fora_push_only(g: Graph, src: int, alpha: float, rmax: float,

@@ -1,0 +1,108 @@
+"""Top-k FORA (Algorithm 5) on the GPU against the oracle: the same number
+of iterations and final delta, the same top-k up to rounding near ties, per
+query decisions in a mixed batch, and Definition 2 against the exact PPR."""
+import numpy as np
+import pytest
+import scipy.stats as st
+
+import oracle
+import synth
+from oracle import exact
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1908_10583_amd import fora  # noqa: E402
+
+ALPHA = 0.2
+
+
+@pytest.fixture(scope="module")
+def g1k():
+    return synth.uniform_out_graph(1000, 10, seed=1)
+
+
+@pytest.fixture(scope="module")
+def G1k(g1k):
+    G = fora.Graph.from_numpy(g1k.rowptr, g1k.colidx)
+    yield G
+    G.close()
+
+
+def _clear_decisions(ref, rel=1e-4):
+    return all(abs(t["kth"] - t["bound"]) > rel * t["bound"] for t in ref["trace"])
+
+
+def _same_topk(ids, vals, ref, omega_unit):
+    k = len(ids)
+    rv = ref["topk_vals"][:k]
+    tol = 1e-4 * np.abs(rv) + 4.0 / omega_unit
+    assert np.all(np.abs(vals.astype(np.float64) - rv) <= tol)
+    gap = np.abs(np.diff(np.concatenate([[np.inf], rv, [-np.inf]])))
+    clear = (gap[:-1] > 2 * tol) & (gap[1:] > 2 * tol)
+    assert np.array_equal(ids[clear], ref["topk_ids"][:k][clear])
+
+
+@pytest.mark.parametrize("k", [5, 50])
+def test_topk_matches_oracle(g1k, G1k, k):
+    srcs, seeds = [0, 17, 999], [3, 4, 5]
+    qs = fora.make_queries(srcs, k=k, seed=seeds, n=g1k.n)
+    res, iters, delta = fora.fora_topk_batch(G1k, qs, stats=True)
+    checked = 0
+    for i, (s, sd) in enumerate(zip(srcs, seeds)):
+        ref = oracle.fora_topk(g1k, s, k, seed=sd)
+        if not _clear_decisions(ref):
+            continue
+        checked += 1
+        assert iters[i] == ref["iterations"] and delta[i] == ref["delta"]
+        assert res.stats[i]["omega_unit"] == ref["consts"]["omega_unit"]
+        _same_topk(res.ids[i].cpu().numpy()[:k], res.vals[i].cpu().numpy()[:k], ref,
+                   res.stats[i]["omega_unit"])
+    assert checked >= 2
+
+
+def test_mixed_k_batch_matches_single_queries(g1k, G1k):
+    srcs, ks, seeds = [0, 0, 250, 17], [5, 50, 10, 1], [1, 2, 3, 4]
+    qs = fora.make_queries(srcs, k=ks, seed=seeds, n=g1k.n)
+    res, iters, delta = fora.fora_topk_batch(G1k, qs, kmax=50, stats=True)
+    for i in range(4):
+        one, it1, d1 = fora.fora_topk_batch(G1k, fora.make_queries([srcs[i]], k=ks[i],
+                                                                   seed=seeds[i], n=g1k.n),
+                                            stats=True)
+        ref = oracle.fora_topk(g1k, srcs[i], ks[i], seed=seeds[i])
+        if _clear_decisions(ref):
+            assert iters[i] == it1[0] == ref["iterations"] and delta[i] == d1[0]
+        a = res.vals[i].cpu().numpy()[:ks[i]].astype(np.float64)
+        b = one.vals[0].cpu().numpy()[:ks[i]].astype(np.float64)
+        np.testing.assert_allclose(a, b, rtol=1e-4, atol=4.0 / res.stats[i]["omega_unit"])
+
+
+def test_definition_2_on_gpu(g1k, G1k):
+    pi = exact.dense_ppr(g1k, ALPHA)[0]
+    order = np.sort(pi)[::-1]
+    k, R, eps = 10, 32, 0.5
+    qs = fora.make_queries([0] * R, k=k, seed=[100 * r for r in range(R)], n=g1k.n)
+    res, iters, delta = fora.fora_topk_batch(G1k, qs)
+    ids = res.ids.cpu().numpy()[:, :k]
+    vals = res.vals.cpu().numpy()[:, :k].astype(np.float64)
+    viol = trials = 0
+    for r in range(R):
+        for i in range(k):
+            if order[i] > 1.0 / g1k.n:
+                trials += 1
+                ok = vals[r, i] >= (1 - eps) * pi[ids[r, i]] and \
+                    pi[ids[r, i]] >= (1 - eps) * order[i]
+                viol += not ok
+    assert viol <= st.binom(trials, 1.0 / g1k.n).ppf(1 - 1e-6)
+    assert np.all(iters >= 1) and np.all(delta >= 1.0 / g1k.n)
+
+
+def test_topk_workspace_is_checked(g1k, G1k):
+    qs = fora.make_queries([0], k=5, n=g1k.n)
+    small = torch.empty(fora.fora_workspace_size(G1k, 1), dtype=torch.uint8, device="cuda")
+    with pytest.raises(fora.FORAError) as ei:
+        fora.fora_topk_batch(G1k, qs, ws=small)
+    assert ei.value.code == fora.FORA_E_NOMEM
