@@ -83,6 +83,7 @@ def main():
                     help="use only the workload's first N sources (0: all)")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
     ap.add_argument("--no-alg3", action="store_true", help="skip the Algorithm 3 leg")
+    ap.add_argument("--no-topk", action="store_true", help="skip the top-k FORA leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy, whose HBM counter "
                          "readings calibrate FETCH_SIZE / WRITE_SIZE")
@@ -244,6 +245,33 @@ def main():
                     walks=sum(x["walks"] for x in st3))
         log(f"Algorithm 3 (pruned + balanced, walk_cost {wc:.2f}): {alg3['queries_per_s']} q/s")
 
+    topk_leg = None
+    if not args.no_topk:
+        # top-k FORA (Algorithm 5): the same sources and k, eps and p_f of the
+        # workload, delta halving from 1/k until the k-th estimate clears it
+        qk = fora.make_queries(srcs[:WB], alpha=alpha, eps=eps, k=k, seed=seed, n=g.n)
+        wsk = torch.empty(fora.fora_topk_workspace_size(G, len(qk), k), dtype=torch.uint8,
+                          device="cuda:0")
+        outk = (ids[:len(qk)], vals[:len(qk)])
+        for _ in range(args.warmup):
+            fora.fora_topk_batch(G, qk, kmax=k, ws=wsk, out=outk)
+        torch.cuda.synchronize()
+        tk = time.perf_counter()
+        for _ in range(args.steps):
+            rk, itk, dk = fora.fora_topk_batch(G, qk, kmax=k, ws=wsk, out=outk, stats=True)
+        torch.cuda.synchronize()
+        dtk = time.perf_counter() - tk
+        topk_leg = dict(queries_per_s=round(len(qk) * args.steps / dtk, 2),
+                        ms_per_step=round(dtk / args.steps * 1e3, 3),
+                        iterations_mean=float(np.mean(itk)),
+                        final_delta_median=float(np.median(dk)),
+                        walks=sum(x["walks"] for x in rk.stats),
+                        note="approximate top-k (Definition 2) by Algorithm 5, not the "
+                             "whole-graph query; sources of the first wave")
+        del wsk
+        log(f"top-k FORA (Algorithm 5): {topk_leg['queries_per_s']} q/s, "
+            f"{topk_leg['iterations_mean']:.1f} iterations")
+
     graph_mode = None
     if graph_rounds > 0 and not args.no_graph:
         G.set_tuning(graph_rounds=graph_rounds)
@@ -298,6 +326,7 @@ def main():
         "plain_single_query": single,
         "batched_learned_rmax": learned_leg,
         "batched_alg3": alg3,
+        "topk_fora": topk_leg,
         "graph_replay": graph_mode,
         "tuning": tuning,
         "phases_ms": {p: round(float(v), 3) for p, v in ph.items()},
