@@ -247,7 +247,7 @@ def topk(pi: np.ndarray, k: int):
 def fora(g, s: int, alpha: float = 0.2, eps: float = 0.5, delta: float | None = None,
          pf: float | None = None, k: int = 500, seed: int = 0,
          rmax: float | None = None, log_frontiers: bool = False, prune: bool = False,
-         walk_cost: float | None = None) -> dict:
+         walk_cost: float | None = None, walk_key=None) -> dict:
     """Whole-graph FORA (Algorithm 2) followed by top-k selection.
 
     prune: Algorithm 3's zero-hop pruning (section 5.1): pi_hat starts at
@@ -255,7 +255,10 @@ def fora(g, s: int, alpha: float = 0.2, eps: float = 0.5, delta: float | None = 
     with r' = (1 - alpha) r start at a random out-neighbour of v, each adding
     r'(v) / omega_v at its end point.
     walk_cost: Algorithm 3's balance rule (section 5.2), the cost of one walk
-    in edge-operation units (None: plain Algorithm 1)."""
+    in edge-operation units (None: plain Algorithm 1).
+    walk_key: (key0, key1) of the walks instead of (s, seed): the walks of an
+    index shared by all sources (FORA+, section 3.3); walk j from v is then
+    the j-th pre-computed walk of v whoever the source is."""
     n = g.n
     delta = 1.0 / n if delta is None else delta
     pf = 1.0 / n if pf is None else pf
@@ -269,7 +272,8 @@ def fora(g, s: int, alpha: float = 0.2, eps: float = 0.5, delta: float | None = 
                            log_frontiers=log_frontiers)
     r_walk = (1.0 - alpha) * ps["r"] if prune else ps["r"]
     pv, po, pw = plan(r_walk, c["omega_unit"])
-    wk = walks(g, s, seed, c["t_alpha"], pv, po, pw, first_move=prune)
+    k0, k1 = (s, seed) if walk_key is None else walk_key
+    wk = walks(g, k0, k1, c["t_alpha"], pv, po, pw, first_move=prune)
     pi = ps["q"] + wk["acc"] + (alpha * ps["r"] if prune else 0.0)
     ids, vals = topk(pi, min(k, n))
     out = dict(consts=c, plan=(pv, po, pw), pi=pi, topk_ids=ids, topk_vals=vals,
@@ -313,3 +317,19 @@ def fora_topk(g, s: int, k: int, alpha: float = 0.2, eps: float = 0.5, pf: float
     out = dict(out)
     out.update(iterations=len(trace), delta=trace[-1]["delta"], trace=trace, pf_iter=pf_it)
     return out
+
+
+def build_index(g, alpha: float, walks_per_degree: float, key) -> dict:
+    """FORA+'s walk-destination index (section 3.3, eqn:index-rwnum): for
+    every node v, omega_max(v) = ceil(d(v) walks_per_degree) walks (with
+    walks_per_degree = r_max omega_unit) keyed by (key0, key1) and walk
+    index j; their end points in (v, j) order, and the offsets."""
+    n = g.n
+    deg = g.degrees().astype(np.float64)
+    om = np.ceil(deg * walks_per_degree).astype(np.uint64)
+    off = np.zeros(n + 1, np.uint64)
+    off[1:] = np.cumsum(om)
+    t_alpha = int(math.floor(alpha * 2.0**32))
+    pv = np.arange(n, dtype=np.int32)
+    wk = walks(g, key[0], key[1], t_alpha, pv, om, np.ones(n), endpoints=True)
+    return dict(off=off, dest=wk["endpoints"], omega_max=om)
