@@ -96,6 +96,13 @@ typedef struct fora_query {
  *   bounds the push from below. */
 #define FORA_PRUNE_ZERO_HOP 1u
 #define FORA_BALANCE 2u
+/* FORA+ (section 3.3): walk j of v comes from the graph's walk-destination
+ * index when j < omega_max(v) (fora_build_index); walks are then keyed by
+ * the index key instead of (source, seed), and later ones run live with that
+ * key, so results equal running all walks with the index key. Needs an
+ * index built for the query's alpha; not combined with
+ * FORA_PRUNE_ZERO_HOP. */
+#define FORA_USE_INDEX 4u
 
 #define FORA_MAX_K 4096
 #define FORA_MAX_BATCH 4096
@@ -193,6 +200,21 @@ int fora_ssppr_batch(const fora_graph *g, int32_t batch,
                      fora_stats *h_stats, void *stream);
 
 /* ---- step-level entry points (used to compare each phase on its own) ---- */
+
+/* ---- FORA+ walk-destination index (section 3.3) ---------------------------
+ * Builds (or replaces) the graph's index: for every node v,
+ * omega_max(v) = ceil(d(v) walks_per_degree) walks (eqn:index-rwnum with
+ * walks_per_degree = r_max omega_unit) keyed by (key0, key1) and walk index,
+ * stopping with probability alpha; their end points are stored in (v, j)
+ * order. Allocates the index (8 (n + 1) + 4 sum omega_max bytes) and waits.
+ * FORA_E_OVERFLOW if some omega_max(v) >= 2^32. */
+int fora_build_index(fora_graph *g, double alpha, double walks_per_degree, uint32_t key0,
+                     uint32_t key1, void *stream);
+/* The index's parameters and total end points (0 if none). */
+int fora_index_info(const fora_graph *g, int64_t *total, double *alpha,
+                    double *walks_per_degree, uint32_t *key0, uint32_t *key1);
+/* Copies the index: d_off uint64[n + 1] and d_dest int32[total] (device). */
+int fora_index_export(const fora_graph *g, uint64_t *d_off, int32_t *d_dest, void *stream);
 
 /* ---- top-k FORA (Algorithm 5, section 6.2) ------------------------------
  * For each query, with its own k: run Algorithm 2 with eps' = eps / 2,

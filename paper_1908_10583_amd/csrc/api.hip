@@ -30,6 +30,12 @@ struct fora_graph {
   uint32_t* rec_owned = nullptr;
   uint32_t* rec_q_owned = nullptr;
   int32_t* rank_owned = nullptr;
+  // FORA+ index
+  fora::u64* idx_off_owned = nullptr;
+  int32_t* idx_dest_owned = nullptr;
+  int64_t idx_total = 0;
+  double idx_alpha = 0.0, idx_wpd = 0.0;
+  uint32_t idx_key0 = 0, idx_key1 = 0;
   int device = 0;
   int cus = 256;
   // pinned host slots for the small read-backs of the push loop
@@ -92,8 +98,15 @@ int check_query(const fora_graph* g, const fora_query& q) {
   if (!(q.pf > 0.0 && q.pf < 1.0)) return fail(FORA_E_ARG, "pf must be in (0,1)");
   if (q.k < 1 || q.k > n || q.k > FORA_MAX_K) return fail(FORA_E_ARG, "k must be in [1, min(n, FORA_MAX_K)]");
   if (!(q.rmax <= 0.0 || std::isfinite(q.rmax))) return fail(FORA_E_ARG, "rmax must be finite");
-  if ((q.flags & ~(FORA_PRUNE_ZERO_HOP | FORA_BALANCE)) != 0 || q.reserved != 0)
+  if ((q.flags & ~(FORA_PRUNE_ZERO_HOP | FORA_BALANCE | FORA_USE_INDEX)) != 0 || q.reserved != 0)
     return fail(FORA_E_ARG, "unknown query flags");
+  if (q.flags & FORA_USE_INDEX) {
+    if (!g->idx_dest_owned) return fail(FORA_E_ARG, "FORA_USE_INDEX without an index");
+    if (std::floor(std::ldexp(q.alpha, 32)) != std::floor(std::ldexp(g->idx_alpha, 32)))
+      return fail(FORA_E_ARG, "the index was built for another alpha");
+    if (q.flags & FORA_PRUNE_ZERO_HOP)
+      return fail(FORA_E_ARG, "FORA_USE_INDEX does not combine with FORA_PRUNE_ZERO_HOP");
+  }
   if ((q.flags & FORA_BALANCE) && !(q.walk_cost >= 0.0 && std::isfinite(q.walk_cost)))
     return fail(FORA_E_ARG, "walk_cost must be finite and >= 0");
   return FORA_OK;
@@ -121,6 +134,10 @@ QueryDev plan_query(const fora_graph* g, const fora_query& q) {
   d.t_alpha = (uint32_t)std::floor(std::ldexp(q.alpha, 32));
   d.flags = q.flags;
   d.walk_cost = (q.flags & FORA_BALANCE) ? q.walk_cost : 0.0;
+  if (q.flags & FORA_USE_INDEX) {  // the index's walks: keyed by the index key
+    d.key0 = g->idx_key0;
+    d.key1 = g->idx_key1;
+  }
   return d;
 }
 
@@ -631,6 +648,8 @@ int fora_build_csr(int32_t n, int64_t m, const int32_t* d_rowptr, const int32_t*
     if (g->rec_owned) (void)hipFree(g->rec_owned);
     if (g->rec_q_owned) (void)hipFree(g->rec_q_owned);
     if (g->rank_owned) (void)hipFree(g->rank_owned);
+    if (g->idx_off_owned) (void)hipFree(g->idx_off_owned);
+    if (g->idx_dest_owned) (void)hipFree(g->idx_dest_owned);
     if (g->info_owned) (void)hipFree(g->info_owned);
     if (g->flags_owned) (void)hipFree(g->flags_owned);
     if (g->pinned) (void)hipHostFree(g->pinned);
@@ -708,6 +727,8 @@ int fora_free_graph(fora_graph* g) {
   if (g->rec_owned) (void)hipFree(g->rec_owned);
   if (g->rec_q_owned) (void)hipFree(g->rec_q_owned);
   if (g->rank_owned) (void)hipFree(g->rank_owned);
+  if (g->idx_off_owned) (void)hipFree(g->idx_off_owned);
+  if (g->idx_dest_owned) (void)hipFree(g->idx_dest_owned);
   if (g->info_owned) (void)hipFree(g->info_owned);
   if (g->flags_owned) (void)hipFree(g->flags_owned);
   if (g->pinned) (void)hipHostFree(g->pinned);
@@ -767,6 +788,120 @@ int fora_ssppr_batch(const fora_graph* g, int32_t batch, const fora_query* h_que
   if (kmax < 1 || kmax > FORA_MAX_K) return fail(FORA_E_ARG, "kmax out of range");
   return run_queries(const_cast<fora_graph*>(g), batch, h_queries, kmax, d_ws, ws_bytes, d_ids,
                      d_vals, h_stats, (hipStream_t)stream);
+}
+
+int fora_build_index(fora_graph* g, double alpha, double walks_per_degree, uint32_t key0,
+                     uint32_t key1, void* stream) {
+  if (!g) return fail(FORA_E_ARG, "null graph");
+  if (!(alpha > 0.0 && alpha < 1.0)) return fail(FORA_E_ARG, "alpha must be in (0,1)");
+  if (!(walks_per_degree >= 0.0 && std::isfinite(walks_per_degree)))
+    return fail(FORA_E_ARG, "walks_per_degree must be finite and >= 0");
+  if (std::ceil((double)g->dev.max_deg * walks_per_degree) >= 4294967296.0)
+    return fail(FORA_E_OVERFLOW, "omega_max(v) >= 2^32 for the largest degree");
+  hipStream_t s = (hipStream_t)stream;
+  FORA_HIP(hipSetDevice(g->device));
+  drop_graphs(g);  // captured pipelines hold the old index pointers
+  if (g->idx_off_owned) (void)hipFree(g->idx_off_owned);
+  if (g->idx_dest_owned) (void)hipFree(g->idx_dest_owned);
+  g->idx_off_owned = nullptr;
+  g->idx_dest_owned = nullptr;
+  g->dev.idx_off = nullptr;
+  g->dev.idx_dest = nullptr;
+  g->idx_total = 0;
+  const int64_t n = g->dev.n;
+  const int64_t tiles = (n + 2047) / 2048;
+  u64 *off = nullptr, *plan_gi = nullptr, *tsum = nullptr;
+  Ctrl* ctrl = nullptr;
+  QueryDev* qd = nullptr;
+  StatSlot* qs = nullptr;
+  int32_t* dest = nullptr;
+  auto release = [&](bool keep) {
+    if (plan_gi) (void)hipFree(plan_gi);
+    if (tsum) (void)hipFree(tsum);
+    if (ctrl) (void)hipFree(ctrl);
+    if (qd) (void)hipFree(qd);
+    if (qs) (void)hipFree(qs);
+    if (!keep) {
+      if (off) (void)hipFree(off);
+      if (dest) (void)hipFree(dest);
+    }
+  };
+  if (hipMalloc(&off, sizeof(u64) * (size_t)(n + 1)) != hipSuccess ||
+      hipMalloc(&plan_gi, sizeof(u64) * (size_t)n) != hipSuccess ||
+      hipMalloc(&tsum, sizeof(u64) * (size_t)tiles) != hipSuccess ||
+      hipMalloc(&ctrl, sizeof(Ctrl)) != hipSuccess ||
+      hipMalloc(&qd, sizeof(QueryDev)) != hipSuccess ||
+      hipMalloc(&qs, sizeof(StatSlot) * kStatSlots) != hipSuccess) {
+    release(false);
+    return fail(FORA_E_NOMEM, "hipMalloc for the index build failed");
+  }
+  u64 total = 0;
+  hipError_t e = launch_index_plan(g->dev, walks_per_degree, off, plan_gi, tsum, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&total, off + n, sizeof(u64), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    release(false);
+    return fail(FORA_E_HIP, std::string("index plan: ") + hipGetErrorString(e));
+  }
+  if (hipMalloc(&dest, sizeof(int32_t) * (size_t)std::max<u64>(total, 1)) != hipSuccess) {
+    release(false);
+    return fail(FORA_E_NOMEM, "hipMalloc of the index failed");
+  }
+  std::vector<unsigned char> zero(sizeof(Ctrl), 0);
+  Ctrl* hc = reinterpret_cast<Ctrl*>(zero.data());
+  hc->walks = total;
+  hc->entries = (u64)n;
+  QueryDev hq{};
+  hq.key0 = key0;
+  hq.key1 = key1;
+  hq.alpha = alpha;
+  hq.t_alpha = (uint32_t)std::floor(std::ldexp(alpha, 32));
+  e = hipMemcpyAsync(ctrl, zero.data(), sizeof(Ctrl), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(qd, &hq, sizeof(QueryDev), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_fill_zero(qs, sizeof(StatSlot) * kStatSlots, s);
+  if (e == hipSuccess && total > 0)
+    e = launch_index_walks(g->dev, plan_gi, off, ctrl, qd, qs, dest, walk_blocks(g),
+                           walk_chunk(g), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    release(false);
+    return fail(FORA_E_HIP, std::string("index walks: ") + hipGetErrorString(e));
+  }
+  release(true);
+  g->idx_off_owned = off;
+  g->idx_dest_owned = dest;
+  g->idx_total = (int64_t)total;
+  g->idx_alpha = alpha;
+  g->idx_wpd = walks_per_degree;
+  g->idx_key0 = key0;
+  g->idx_key1 = key1;
+  g->dev.idx_off = off;
+  g->dev.idx_dest = dest;
+  return FORA_OK;
+}
+
+int fora_index_info(const fora_graph* g, int64_t* total, double* alpha, double* walks_per_degree,
+                    uint32_t* key0, uint32_t* key1) {
+  if (!g) return fail(FORA_E_ARG, "null graph");
+  if (total) *total = g->idx_dest_owned ? g->idx_total : 0;
+  if (alpha) *alpha = g->idx_alpha;
+  if (walks_per_degree) *walks_per_degree = g->idx_wpd;
+  if (key0) *key0 = g->idx_key0;
+  if (key1) *key1 = g->idx_key1;
+  return FORA_OK;
+}
+
+int fora_index_export(const fora_graph* g, uint64_t* d_off, int32_t* d_dest, void* stream) {
+  if (!g || !d_off || !d_dest) return fail(FORA_E_ARG, "null argument");
+  if (!g->idx_dest_owned) return fail(FORA_E_ARG, "no index");
+  hipStream_t s = (hipStream_t)stream;
+  FORA_HIP(hipMemcpyAsync(d_off, g->idx_off_owned, sizeof(u64) * ((size_t)g->dev.n + 1),
+                          hipMemcpyDeviceToDevice, s));
+  if (g->idx_total > 0)
+    FORA_HIP(hipMemcpyAsync(d_dest, g->idx_dest_owned, sizeof(int32_t) * (size_t)g->idx_total,
+                            hipMemcpyDeviceToDevice, s));
+  FORA_HIP(hipStreamSynchronize(s));
+  return FORA_OK;
 }
 
 int fora_topk_workspace_size(const fora_graph* g, int32_t batch, int32_t kmax, size_t* bytes) {

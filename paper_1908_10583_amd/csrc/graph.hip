@@ -189,6 +189,70 @@ hipError_t launch_build_reverse(const GraphDev& g, int32_t* in_rowptr, int32_t* 
   return hipGetLastError();
 }
 
+// FORA+ index plan: omega_max(v) = ceil(d(v) walks_per_degree) (FP64),
+// exclusive prefix in 64 bits (tile sums, one-block scan, apply).
+__global__ __launch_bounds__(256) void k_index_count(const int2* __restrict__ info, int32_t n,
+                                                     double wpd, u64* om, u64* plan_gi,
+                                                     u64* tsum) {
+  __shared__ u64 s_tmp[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  u64 acc = 0;
+  for (int k = threadIdx.x; k < kScanTile; k += 256) {
+    const int64_t v = base + k;
+    if (v < n) {
+      const u64 c = (u64)ceil((double)info[v].y * wpd);
+      om[v] = c;
+      plan_gi[v] = (u64)v;
+      acc += c;
+    }
+  }
+  const u64 t = block_sum(acc, s_tmp);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(1024) void k_tile_scan64(u64* tsum, int64_t ntiles) {
+  __shared__ u64 s_tmp[16];
+  u64 carry = 0;
+  for (int64_t base = 0; base < ntiles; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const u64 c = i < ntiles ? tsum[i] : 0ull;
+    u64 tot;
+    const u64 p = block_exclusive_scan(c, s_tmp, tot);
+    if (i < ntiles) tsum[i] = carry + p;
+    carry += tot;
+  }
+}
+
+// in place: off[v] holds omega_max(v) on entry and its exclusive prefix on
+// exit; off[n] = the total
+__global__ __launch_bounds__(256) void k_tile_apply64(u64* off, int64_t n, const u64* tsum) {
+  __shared__ u64 s_tmp[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 8;
+  u64 v[8], loc = 0;
+  for (int k = 0; k < 8; ++k) {
+    v[k] = base + k < n ? off[base + k] : 0ull;
+    loc += v[k];
+  }
+  u64 tot;
+  u64 run = tsum[blockIdx.x] + block_exclusive_scan(loc, s_tmp, tot);
+  for (int k = 0; k < 8; ++k) {
+    if (base + k < n) off[base + k] = run;
+    if (base + k == n - 1) off[n] = run + v[k];
+    run += v[k];
+  }
+}
+
+hipError_t launch_index_plan(const GraphDev& g, double walks_per_degree, u64* off, u64* plan_gi,
+                             u64* scratch, hipStream_t s) {
+  const int64_t n = g.n;
+  const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  k_index_count<<<(unsigned)tiles, 256, 0, s>>>(g.info, g.n, walks_per_degree, off, plan_gi,
+                                                scratch);
+  k_tile_scan64<<<1, 1024, 0, s>>>(scratch, tiles);
+  k_tile_apply64<<<(unsigned)tiles, 256, 0, s>>>(off, n, scratch);
+  return hipGetLastError();
+}
+
 // Degree rank: sort (out-degree, id) pairs by degree, descending (the sort is
 // stable, so equal degrees keep id order), then rank[order[i]] = i.
 __global__ void k_deg_keys(const int2* __restrict__ info, int32_t n, int32_t* key, int32_t* id) {

@@ -118,6 +118,9 @@ struct GraphDev {
   // in the dense pull-increment rows, and the order of the walk records, so
   // that the values read most often (those of high-degree nodes) share lines
   const int32_t* rank;
+  // FORA+ walk-destination index (null if none): offsets (n + 1) and end points
+  const u64* idx_off;
+  const int32_t* idx_dest;
 };
 
 struct Layout {
@@ -213,6 +216,13 @@ hipError_t launch_topk(const GraphDev& g, const Ws& w, const Layout& L, int batc
                        int kmax, int32_t* d_ids, float* d_vals, hipStream_t s);
 hipError_t launch_build_reverse(const GraphDev& g, int32_t* in_rowptr, int32_t* in_colidx,
                                 int32_t* cursor, uint32_t* tsum, hipStream_t s);
+hipError_t launch_index_walks(const GraphDev& g, const u64* plan_gi, const u64* off, Ctrl* ctrl,
+                              const QueryDev* Q, QueryStatsDev* QS, int32_t* dest, int blocks,
+                              int chunk, hipStream_t s);
+// omega_max(v) = ceil(d(v) walks_per_degree) and its exclusive prefix into
+// off[n + 1]; plan_gi[v] = v. scratch: ceil(n / 2048) u64.
+hipError_t launch_index_plan(const GraphDev& g, double walks_per_degree, u64* off, u64* plan_gi,
+                             u64* scratch, hipStream_t s);
 hipError_t launch_topk_kth(const float* vals, int kmax, const int32_t* ks, int count, float* kth,
                            hipStream_t s);
 hipError_t launch_copy_rows(const int32_t* src_ids, const float* src_vals, int kmax,

@@ -10,6 +10,11 @@
 // With FORA_PRUNE_ZERO_HOP (Algorithm 3) the step-0 block only chooses the
 // first move: every walk starts at a random out-neighbour of v.
 //
+// With FORA_USE_INDEX (FORA+, section 3.3) walk j of v, if j < omega_max(v),
+// is read from the graph's walk-destination index instead of being run: the
+// index holds the end points of the same walks (keyed by the index key), so
+// results are the same as running them. STORE builds that index.
+//
 // With AGG, a wave first adds its end points to a wave-private LDS table
 // keyed by (query, node) and moves the table's sums to HBM when it holds
 // kAggFlushAt keys and at the end; repeated end points (walks from one start
@@ -104,13 +109,15 @@ __device__ __forceinline__ u64 wave_find_entry(const u64* __restrict__ off, u64 
   return lo + (u64)(63 - __builtin_clzll(mask));
 }
 
-template <bool AGG>
+// STORE: the index build; walk g's end point goes to store[g] (no weights).
+template <bool AGG, bool STORE>
 __global__ __launch_bounds__(kWalkBlock) void k_walks(
     const u64* __restrict__ plan_gi, const u64* __restrict__ plan_off,
     const u64* __restrict__ plan_wfx, Ctrl* ctrl, const QueryDev* __restrict__ Q,
     QueryStatsDev* QS, const int2* __restrict__ info, const uint32_t* __restrict__ rec,
-    const uint32_t* __restrict__ rec_q, int n, u64* __restrict__ cnt, u64* __restrict__ acc,
-    int chunk) {
+    const uint32_t* __restrict__ rec_q, const u64* __restrict__ idx_off,
+    const int32_t* __restrict__ idx_dest, int n, u64* __restrict__ cnt, u64* __restrict__ acc,
+    int32_t* __restrict__ store, int chunk) {
   __shared__ u64 s_agg[AGG ? 3 * kWalkWaves * kAggSlots : 1];
   if (ctrl->error || ctrl->skip) return;
   const u64 W = ctrl->walks;
@@ -137,6 +144,8 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
   int32_t x = 0;
   uint32_t q = 0, deg = 1;  // record start and out-degree of x
   bool forced = false;      // FORA_PRUNE_ZERO_HOP: the next step must move
+  bool indexed = false;     // FORA_USE_INDEX: x is the stored end point of the walk
+  u64 gid = 0;              // the walk's global id (STORE)
   u64 wfx = 0;
   int stat_b = -1;
   u64 stat_steps = 0;
@@ -181,18 +190,30 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
         if (!active && rank < nassign) {
           const u64 e = ebase + (u64)lo;
           const u64 gi = plan_gi[e];
-          wfx = plan_wfx[e];
+          wfx = STORE ? 0ull : plan_wfx[e];
           b = (int)(gi >> 32);
           v = (uint32_t)gi;
           j = (uint32_t)(id - o_lo);
+          gid = id;
           x = (int32_t)v;
-          deg = (uint32_t)info[v].y;
-          q = rec_q[v];
           step = 0;
           k0 = Q[b].key0;
           k1 = Q[b].key1;
           ta = Q[b].t_alpha;
           forced = (Q[b].flags & FORA_PRUNE_ZERO_HOP) != 0;
+          indexed = false;
+          if (!STORE && (Q[b].flags & FORA_USE_INDEX)) {
+            // walk j of v is stored if j < omega_max(v); later ones run live
+            const u64 o0 = idx_off[v];
+            if ((u64)j < idx_off[v + 1] - o0) {
+              x = idx_dest[o0 + j];
+              indexed = true;
+            }
+          }
+          if (!indexed) {
+            deg = (uint32_t)info[v].y;
+            q = rec_q[v];
+          }
           active = true;
         }
         cursor += nassign;
@@ -220,10 +241,13 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
     }
     bool fresh = false;
     if (active) {
-      const uint4 y = philox4x32_10(make_uint4(v, j, step, 0u), k0, k1);
-      if (!forced && y.x < ta) {
+      uint4 y = make_uint4(0u, 0u, 0u, 0u);
+      if (!indexed) y = philox4x32_10(make_uint4(v, j, step, 0u), k0, k1);
+      if (indexed || (!forced && y.x < ta)) {
         const size_t t = (size_t)b * n + x;
-        if (!AGG || !agg_add(agg, (u64)t, wfx, &fresh)) {
+        if (STORE) {
+          store[gid] = x;
+        } else if (!AGG || !agg_add(agg, (u64)t, wfx, &fresh)) {
           atomicAdd(&cnt[t], 1ull);
           atomicAdd(&acc[t], wfx);
         }
@@ -261,13 +285,24 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
 hipError_t launch_walks(const GraphDev& g, const Ws& w, int blocks, int chunk, bool agg,
                         hipStream_t s) {
   if (agg)
-    k_walks<true><<<blocks, kWalkBlock, 0, s>>>(w.plan_gi, w.plan_off, w.plan_wfx, w.ctrl,
-                                                w.queries, w.qstats, g.info, g.rec, g.rec_q, g.n,
-                                                w.cnt, w.acc, chunk);
+    k_walks<true, false><<<blocks, kWalkBlock, 0, s>>>(
+        w.plan_gi, w.plan_off, w.plan_wfx, w.ctrl, w.queries, w.qstats, g.info, g.rec, g.rec_q,
+        g.idx_off, g.idx_dest, g.n, w.cnt, w.acc, nullptr, chunk);
   else
-    k_walks<false><<<blocks, kWalkBlock, 0, s>>>(w.plan_gi, w.plan_off, w.plan_wfx, w.ctrl,
-                                                 w.queries, w.qstats, g.info, g.rec, g.rec_q,
-                                                 g.n, w.cnt, w.acc, chunk);
+    k_walks<false, false><<<blocks, kWalkBlock, 0, s>>>(
+        w.plan_gi, w.plan_off, w.plan_wfx, w.ctrl, w.queries, w.qstats, g.info, g.rec, g.rec_q,
+        g.idx_off, g.idx_dest, g.n, w.cnt, w.acc, nullptr, chunk);
+  return hipGetLastError();
+}
+
+// The index build: plan (v, omega_max(v)) for every node with offsets off,
+// one query entry Q (the index key), end points into dest.
+hipError_t launch_index_walks(const GraphDev& g, const u64* plan_gi, const u64* off, Ctrl* ctrl,
+                              const QueryDev* Q, QueryStatsDev* QS, int32_t* dest, int blocks,
+                              int chunk, hipStream_t s) {
+  k_walks<false, true><<<blocks, kWalkBlock, 0, s>>>(plan_gi, off, nullptr, ctrl, Q, QS, g.info,
+                                                     g.rec, g.rec_q, nullptr, nullptr, g.n,
+                                                     nullptr, nullptr, dest, chunk);
   return hipGetLastError();
 }
 

@@ -88,6 +88,11 @@ def _load():
                         ctypes.POINTER(fora_stats), P], ctypes.c_int),
         "fora_ssppr_batch": ([P, I32, ctypes.POINTER(fora_query), I32, P, SZ, P, P,
                               ctypes.POINTER(fora_stats), P], ctypes.c_int),
+        "fora_build_index": ([P, F64, F64, ctypes.c_uint32, ctypes.c_uint32, P], ctypes.c_int),
+        "fora_index_info": ([P, ctypes.POINTER(I64), ctypes.POINTER(F64), ctypes.POINTER(F64),
+                             ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)],
+                            ctypes.c_int),
+        "fora_index_export": ([P, P, P, P], ctypes.c_int),
         "fora_topk_workspace_size": ([P, I32, I32, ctypes.POINTER(SZ)], ctypes.c_int),
         "fora_topk_batch": ([P, I32, ctypes.POINTER(fora_query), I32, P, SZ, P, P,
                              ctypes.POINTER(fora_stats), P, P, P], ctypes.c_int),
@@ -123,10 +128,12 @@ EXPORTED = ["fora_last_error", "fora_build_csr", "fora_free_graph", "fora_graph_
             "fora_push_only", "fora_walk_only", "fora_philox", "fora_features",
             "fora_mlp_forward", "fora_mlp_backward", "fora_adam_step", "fora_mlp_to_bf16",
             "fora_mlp_forward_bf16", "fora_predict_rmax", "fora_push_sweep",
-            "fora_topk_workspace_size", "fora_topk_batch"]
+            "fora_topk_workspace_size", "fora_topk_batch", "fora_build_index",
+            "fora_index_info", "fora_index_export"]
 
 FORA_PRUNE_ZERO_HOP = 1
 FORA_BALANCE = 2
+FORA_USE_INDEX = 4
 FORA_MLP_FEATURES = 7
 FORA_MLP_PARAMS = 4751
 FORA_MLP_ACTS = 128
@@ -312,6 +319,32 @@ def fora_ssppr_batch(g: Graph, queries, kmax: int | None = None,
     _check(_lib.fora_ssppr_batch(g.handle, B, queries, kmax, _ptr(ws), ws.numel(), _ptr(ids),
                                  _ptr(vals), st, ctypes.c_void_p(_stream(stream))))
     return Result(ids, vals, [s.as_dict() for s in st] if st is not None else None)
+
+
+def fora_build_index(g: Graph, alpha: float, walks_per_degree: float, key0: int, key1: int,
+                     stream=None):
+    """Builds the graph's FORA+ walk-destination index (section 3.3)."""
+    _check(_lib.fora_build_index(g.handle, alpha, walks_per_degree, key0 & 0xFFFFFFFF,
+                                 key1 & 0xFFFFFFFF, ctypes.c_void_p(_stream(stream))))
+
+
+def fora_index_info(g: Graph) -> dict:
+    t, a, w = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    k0, k1 = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(_lib.fora_index_info(g.handle, ctypes.byref(t), ctypes.byref(a), ctypes.byref(w),
+                                ctypes.byref(k0), ctypes.byref(k1)))
+    return dict(total=t.value, alpha=a.value, walks_per_degree=w.value, key=(k0.value, k1.value))
+
+
+def fora_index_export(g: Graph, stream=None):
+    """Copies of the index: offsets (int64 tensor holding uint64, n + 1) and
+    end points (int32 tensor)."""
+    total = fora_index_info(g)["total"]
+    off = torch.empty(g.n + 1, dtype=torch.int64, device=g.device)
+    dest = torch.empty(max(total, 1), dtype=torch.int32, device=g.device)
+    _check(_lib.fora_index_export(g.handle, _ptr(off), _ptr(dest),
+                                  ctypes.c_void_p(_stream(stream))))
+    return off, dest[:total]
 
 
 def fora_topk_workspace_size(g: Graph, batch: int, kmax: int) -> int:
