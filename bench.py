@@ -84,6 +84,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
     ap.add_argument("--no-alg3", action="store_true", help="skip the Algorithm 3 leg")
     ap.add_argument("--no-topk", action="store_true", help="skip the top-k FORA leg")
+    ap.add_argument("--no-index", action="store_true", help="skip the FORA+ (index) leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy, whose HBM counter "
                          "readings calibrate FETCH_SIZE / WRITE_SIZE")
@@ -245,6 +246,40 @@ def main():
                     walks=sum(x["walks"] for x in st3))
         log(f"Algorithm 3 (pruned + balanced, walk_cost {wc:.2f}): {alg3['queries_per_s']} q/s")
 
+    index_leg = None
+    if not args.no_index:
+        # FORA+ (section 3.3): an index of omega_max(v) = ceil(d(v) r_max* omega_unit)
+        # walk end points per node, built once; the timed queries read it
+        rstar = stats0[0]["rmax"]
+        wpd = rstar * stats0[0]["omega_unit"]
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        fora.fora_build_index(G, alpha, wpd, 0x5EED, seed)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - tb
+        info = fora.fora_index_info(G)
+        qi = [fora.make_queries(srcs[a:b], alpha=alpha, eps=eps, k=k, seed=seed, n=g.n,
+                                flags=fora.FORA_USE_INDEX) for a, b in waves]
+        for _ in range(args.warmup):
+            run_all(queries=qi)
+        torch.cuda.synchronize()
+        ti = time.perf_counter()
+        for _ in range(args.steps):
+            pwi = run_all(stats=True, queries=qi)
+        torch.cuda.synchronize()
+        dti = time.perf_counter() - ti
+        sti = [x for w in pwi for x in w]
+        index_leg = dict(queries_per_s=round(B * args.steps / dti, 2),
+                         ms_per_step=round(dti / args.steps * 1e3, 3),
+                         phases_ms={p: round(sum(w[0][p] for w in pwi), 3)
+                                    for p in ("ms_push", "ms_plan", "ms_walk", "ms_topk")},
+                         walks=sum(x["walks"] for x in sti),
+                         live_walk_steps=sum(x["steps"] for x in sti),
+                         index_entries=info["total"], index_bytes=info["total"] * 4 + 8 * (g.n + 1),
+                         index_build_s=round(t_build, 3), walks_per_degree=wpd)
+        log(f"FORA+ (index, built in {t_build:.2f}s, {info['total']} entries): "
+            f"{index_leg['queries_per_s']} q/s")
+
     topk_leg = None
     if not args.no_topk:
         # top-k FORA (Algorithm 5): the same sources and k, eps and p_f of the
@@ -327,6 +362,7 @@ def main():
         "batched_learned_rmax": learned_leg,
         "batched_alg3": alg3,
         "topk_fora": topk_leg,
+        "fora_plus_index": index_leg,
         "graph_replay": graph_mode,
         "tuning": tuning,
         "phases_ms": {p: round(float(v), 3) for p, v in ph.items()},
