@@ -253,7 +253,9 @@ int fora_push_only(const fora_graph *g, int32_t src, double alpha, double rmax,
  * (key0, key1) and stop threshold floor(alpha * 2^32). Endpoint counts go to
  * the workspace view walk_count (row 0), weights to walk_weight_fx as
  * round(d_w[e] * 2^62) per walk. h_steps (nullable) receives the move count
- * and makes the call wait. At most n entries. */
+ * and makes the call wait. At most n entries. The plan is checked on the
+ * device before any walk runs: FORA_E_ARG if d_v is not strictly increasing
+ * in [0, n), FORA_E_OVERFLOW for an omega outside [1, 2^32). */
 int fora_walk_only(const fora_graph *g, int64_t entries, const int32_t *d_v,
                    const uint64_t *d_omega, const double *d_w, uint32_t key0,
                    uint32_t key1, double alpha, void *d_ws, size_t ws_bytes,
@@ -280,7 +282,9 @@ int fora_philox(int64_t count, const uint32_t *d_ctr, uint32_t key0,
 /* Features per source, float[count][7]: ln d(s); ln of the summed out-degree
  * of s's out-neighbours; the residue mass on nodes over their threshold after
  * the first synchronous push round at r_max* (0 if s is not pushed); ln n;
- * ln m; alpha; eps. d_srcs int32[count], device. */
+ * ln m; alpha; eps. d_srcs int32[count], device; an id outside [0, n) gets
+ * NaN features (checked on the device), so fora_predict_rmax falls back to
+ * r_max* for it. */
 int fora_features(const fora_graph *g, int32_t count, const int32_t *d_srcs, double alpha,
                   double eps, double delta, double pf, float *d_features, void *stream);
 /* FP32 forward; d_acts (nullable, float[count][FORA_MLP_ACTS]) keeps what the

@@ -142,6 +142,8 @@ QueryDev plan_query(const fora_graph* g, const fora_query& q) {
 }
 
 int error_code_from_flags(int flags) {
+  if (flags & kErrBadPlan)
+    return fail(FORA_E_ARG, "walk plan nodes must be strictly increasing ids in [0, n)");
   if (flags & kErrOmegaOverflow)
     return fail(FORA_E_OVERFLOW, "walk count overflow (some omega_v >= 2^32)");
   if (flags & kErrFrontierOverflow) return fail(FORA_E_OVERFLOW, "frontier overflow");
@@ -167,7 +169,16 @@ void drop_graphs(fora_graph* g) {
 struct Call {
   Layout L;
   Ws w;
+  int walk_chunk = 0;  // walk ids per work-queue grab for this call
 };
+
+// Index walks end at once, so small chunks make the work-queue counter the
+// bottleneck; a call whose queries all read the index grabs larger chunks.
+constexpr int kIndexWalkChunk = 32768;
+
+int call_chunk(const fora_graph* g, const Call& c) {
+  return c.walk_chunk ? c.walk_chunk : g->tuning.walk_chunk;
+}
 
 int prepare(const fora_graph* g, int batch, void* d_ws, size_t ws_bytes, Call& c) {
   if (!g) return fail(FORA_E_ARG, "null graph");
@@ -283,7 +294,8 @@ hipError_t enqueue_pipeline(fora_graph* g, const Call& c, int batch, int rounds,
                           nullptr, 0, s);
   if (e == hipSuccess) e = launch_push_gate(c.w, rounds, s);
   if (e == hipSuccess) e = launch_plan(g->dev, c.w, c.L, batch, s);
-  if (e == hipSuccess) e = launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), g->tuning.walk_agg != 0, s);
+  if (e == hipSuccess) e = launch_walks(g->dev, c.w, walk_blocks(g), call_chunk(g, c),
+                                 g->tuning.walk_agg != 0, s);
   if (e == hipSuccess) e = launch_topk(g->dev, c.w, c.L, batch, kmax, d_ids, d_vals, s);
   return e;
 }
@@ -353,7 +365,8 @@ int run_queries_graph(fora_graph* g, const Call& c, int batch, const std::vector
     rc = run_push(g, c, batch, s, true, nullptr, 0, nullptr, g->tuning.graph_rounds);
     if (rc != FORA_OK) return rc;
     FORA_HIP(launch_plan(g->dev, c.w, c.L, batch, s));
-    FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), g->tuning.walk_agg != 0, s));
+    FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), call_chunk(g, c),
+                                 g->tuning.walk_agg != 0, s));
     FORA_HIP(launch_topk(g->dev, c.w, c.L, batch, kmax, d_ids, d_vals, s));
   }
   return finish(g, c, batch, s, h_stats, qd, nullptr);
@@ -368,12 +381,15 @@ int run_queries(fora_graph* g, int batch, const fora_query* qs, int kmax, void* 
   int rc = prepare(g, batch, d_ws, ws_bytes, c);
   if (rc != FORA_OK) return rc;
   std::vector<QueryDev> qd(batch);
+  bool all_index = true;
   for (int b = 0; b < batch; ++b) {
     rc = check_query(g, qs[b]);
     if (rc != FORA_OK) return rc;
     if (qs[b].k > kmax) return fail(FORA_E_ARG, "kmax smaller than a query's k");
     qd[b] = plan_query(g, qs[b]);
+    all_index = all_index && (qs[b].flags & FORA_USE_INDEX);
   }
+  c.walk_chunk = all_index ? std::max(walk_chunk(g), kIndexWalkChunk) : walk_chunk(g);
   FORA_HIP(hipSetDevice(g->device));
   if (g->tuning.graph_rounds > 0)
     return run_queries_graph(g, c, batch, qd, kmax, d_ws, d_ids, d_vals, h_stats, s);
@@ -388,7 +404,8 @@ int run_queries(fora_graph* g, int batch, const fora_query* qs, int kmax, void* 
   pe.mark(1, s);
   FORA_HIP(launch_plan(g->dev, c.w, c.L, batch, s));
   pe.mark(2, s);
-  FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), g->tuning.walk_agg != 0, s));
+  FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), call_chunk(g, c),
+                                 g->tuning.walk_agg != 0, s));
   pe.mark(3, s);
   FORA_HIP(launch_topk(g->dev, c.w, c.L, batch, kmax, d_ids, d_vals, s));
   pe.mark(4, s);
@@ -1082,7 +1099,8 @@ int fora_walk_only(const fora_graph* gc, int64_t entries, const int32_t* d_v,
   FORA_HIP(hipMemcpyAsync(c.w.queries, &qd, sizeof(qd), hipMemcpyHostToDevice, s));
   if (entries > 0) {
     FORA_HIP(launch_walk_plan_from_host(g->dev, c.w, entries, d_v, d_omega, d_w, s));
-    FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), walk_chunk(g), g->tuning.walk_agg != 0, s));
+    FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), call_chunk(g, c),
+                                 g->tuning.walk_agg != 0, s));
   }
   std::vector<QueryDev> qv(1, qd);
   fora_stats st{};

@@ -49,6 +49,7 @@ enum : int {
   kErrGraphTarget = 16,
   kErrGraphDangling = 32,
   kErrTopk = 64,
+  kErrBadPlan = 128,
 };
 
 struct QueryDev {

@@ -44,6 +44,10 @@ __global__ __launch_bounds__(256) void k_features(const int32_t* __restrict__ sr
   const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (w >= count) return;  // uniform per wave
   const int s = srcs[w];
+  if (s < 0 || s >= n) {  // not a node: NaN features (the predictor then falls back)
+    if (lane < kIn) out[(size_t)w * kIn + lane] = __int_as_float(0x7fc00000);
+    return;
+  }
   const int2 si = info[s];
   const double share = (1.0 - alpha) / (double)si.y;
   const bool pushed = 1.0 > rmax * (double)si.y;

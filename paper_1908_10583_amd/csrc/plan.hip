@@ -206,23 +206,29 @@ hipError_t launch_count_walks(const GraphDev& g, const Ws& w, const Layout& L, i
 
 // ---- a caller-given plan (walk phase on its own) ---------------------------
 // Entries (v, omega, w) for query 0: tile sums of omega, scan, then offsets.
-__global__ __launch_bounds__(kPlanThreads) void k_hplan_count(const uint64_t* omega,
-                                                              int64_t entries,
+// Also checks the caller's nodes: ids in [0, n), strictly increasing (a walk
+// from an id outside the graph would read outside the node table).
+__global__ __launch_bounds__(kPlanThreads) void k_hplan_count(const int32_t* v_in,
+                                                              const uint64_t* omega,
+                                                              int64_t entries, int32_t n,
                                                               uint32_t* tile_cnt,
                                                               u64* tile_walks, Ctrl* ctrl) {
   __shared__ u64 s_tmp[kPlanThreads / 64];
   u64 c = 0, walks = 0;
-  bool bad = false;
+  bool bad = false, bad_v = false;
   for (int k = 0; k < kPlanPerThread; ++k) {
     const int64_t e = (int64_t)blockIdx.x * kPlanTile + threadIdx.x * kPlanPerThread + k;
     if (e < entries) {
       const u64 o = omega[e];
+      const int32_t v = v_in[e];
       bad |= (o == 0) | (o >= 4294967296ull);
+      bad_v |= v < 0 || v >= n || (e > 0 && v <= v_in[e - 1]);
       ++c;
       walks += o;
     }
   }
   if (bad) atomicOr(&ctrl->error, kErrOmegaOverflow);
+  if (bad_v) atomicOr(&ctrl->error, kErrBadPlan);
   const u64 tc = block_sum(c, s_tmp);
   const u64 tw = block_sum(walks, s_tmp);
   if (threadIdx.x == 0) {
@@ -255,11 +261,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_hplan_write(
 hipError_t launch_walk_plan_from_host(const GraphDev& g, const Ws& w, int64_t entries,
                                       const int32_t* d_v, const uint64_t* d_omega,
                                       const double* d_w, hipStream_t s) {
-  (void)g;
+
   const int64_t tiles = (entries + kPlanTile - 1) / kPlanTile;
   if (tiles == 0) return hipSuccess;
-  k_hplan_count<<<(unsigned)tiles, kPlanThreads, 0, s>>>(d_omega, entries, w.tile_cnt,
-                                                         w.tile_walks, w.ctrl);
+  k_hplan_count<<<(unsigned)tiles, kPlanThreads, 0, s>>>(d_v, d_omega, entries, g.n,
+                                                         w.tile_cnt, w.tile_walks, w.ctrl);
   k_plan_scan<<<1, kScanThreads, 0, s>>>(w.tile_cnt, w.tile_walks, tiles, w.tile_eoff,
                                          w.tile_woff, w.plan_off, w.ctrl);
   k_hplan_write<<<(unsigned)tiles, kPlanThreads, 0, s>>>(d_v, d_omega, d_w, entries,

@@ -52,6 +52,19 @@ def test_features_match_reference(grmat, Grmat):
     assert np.count_nonzero(want[:, 2]) > 0  # the residue-mass feature is exercised
 
 
+def test_features_of_non_nodes_are_nan_and_fall_back(grmat, Grmat):
+    n = grmat.n
+    srcs = np.array([0, -5, n, 17], np.int32)
+    f = fora.fora_features(Grmat, _dev(srcs, torch.int32), 0.2, 0.5, 1 / n, 1 / n).cpu().numpy()
+    assert np.all(np.isnan(f[1])) and np.all(np.isnan(f[2])) and np.all(np.isfinite(f[[0, 3]]))
+    pb = fora.fora_mlp_to_bf16(_dev(_params(3, scale=0.01)))
+    rm, fb = fora.fora_predict_rmax(Grmat, _dev(srcs, torch.int32), pb, 0.2, 0.5, 1 / n, 1 / n,
+                                    learned.LOG_LO, learned.LOG_HI)
+    rstar = oracle.constants(grmat.m, 0.2, 0.5, 1 / n, 1 / n)["rmax"]
+    rm = rm.cpu().numpy()
+    assert fb >= 2 and rm[1] == rstar and rm[2] == rstar
+
+
 def test_forward_backward_adam_match_reference():
     rng = np.random.default_rng(5)
     N = 700  # several blocks and a ragged tail

@@ -264,6 +264,20 @@ def test_walk_parity_with_lds_aggregation(grmat12, Grmat12, entries, max_walks, 
         Grmat12.set_tuning(**t0)
 
 
+@pytest.mark.parametrize("bad_v", [[0, 1000], [-1, 3], [5, 5], [7, 3]])
+def test_walk_only_rejects_bad_plans_on_the_device(G1k, bad_v):
+    # node ids outside [0, n) or not strictly increasing: rejected before any
+    # walk reads the node table
+    v = np.array(bad_v, np.int32)
+    with pytest.raises(fora.FORAError) as ei:
+        fora.fora_walk_only(G1k, v, np.ones(2, np.uint64), np.full(2, 0.5), 0, 0, ALPHA)
+    assert ei.value.code == fora.FORA_E_ARG
+    # and the next good call works
+    got = fora.fora_walk_only(G1k, np.array([0, 1], np.int32), np.ones(2, np.uint64),
+                              np.full(2, 0.5), 0, 0, ALPHA)
+    assert int(_cnt(got["cnt"]).sum()) == 2
+
+
 def test_walk_only_empty_plan(G1k):
     got = fora.fora_walk_only(G1k, np.zeros(0, np.int32), np.zeros(0, np.uint64),
                               np.zeros(0), 0, 0, ALPHA)
