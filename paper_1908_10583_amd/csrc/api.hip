@@ -27,7 +27,7 @@ struct fora_graph {
   int32_t* in_colidx_owned = nullptr;
   int32_t* inhub_node_owned = nullptr;
   fora::u64* inhub_base_owned = nullptr;
-  uint32_t* rec_owned = nullptr;
+  uint2* rec_owned = nullptr;
   uint32_t* rec_q_owned = nullptr;
   int32_t* rank_owned = nullptr;
   // FORA+ index
@@ -611,10 +611,12 @@ int build_rank(fora_graph* g, hipStream_t s) {
   return FORA_OK;
 }
 
-// Walk records (one 8-byte header plus one word per out-edge per node).
+// Walk records (one 8-byte header plus one 8-byte unit per out-edge per
+// node); n + m < 2^32 always holds for 32-bit CSR offsets and node ids, so
+// record starts fit 32 bits.
 int build_records(fora_graph* g, hipStream_t s) {
   const int64_t n = g->dev.n;
-  const int64_t words = g->dev.m + 3 * n;  // bound on sum of 2 ceil((2 + d) / 2)
+  const int64_t units = g->dev.m + n;
   const int64_t tiles = (n + 2047) / 2048;
   int32_t* tmp = nullptr;
   uint32_t* tsum = nullptr;
@@ -622,7 +624,7 @@ int build_records(fora_graph* g, hipStream_t s) {
     if (tmp) (void)hipFree(tmp);
     if (tsum) (void)hipFree(tsum);
   };
-  if (hipMalloc(&g->rec_owned, sizeof(uint32_t) * (size_t)words) != hipSuccess ||
+  if (hipMalloc(&g->rec_owned, sizeof(uint2) * (size_t)units) != hipSuccess ||
       hipMalloc(&g->rec_q_owned, sizeof(uint32_t) * ((size_t)n + 1)) != hipSuccess ||
       hipMalloc(&tmp, sizeof(int32_t) * (2 * (size_t)n + 1)) != hipSuccess ||
       hipMalloc(&tsum, sizeof(uint32_t) * (size_t)tiles) != hipSuccess) {

@@ -304,7 +304,7 @@ __global__ void k_rec_len(const int2* __restrict__ info, const int32_t* __restri
                           int32_t n, int32_t* len) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x)
-    len[rank[v]] = (2 + info[v].y + 1) / 2;
+    len[rank[v]] = 1 + info[v].y;
 }
 
 // rec_q[v] = start[rank[v]] (start holds the record starts in rank order)
@@ -317,24 +317,23 @@ __global__ void k_rec_start(const int32_t* __restrict__ rank, int32_t n,
 }
 
 __global__ void k_fill_rec(const int2* __restrict__ info, const int32_t* __restrict__ colidx,
-                           int32_t n, const uint32_t* __restrict__ rec_q, uint32_t* rec) {
+                           int32_t n, const uint32_t* __restrict__ rec_q, uint2* rec) {
   const int lane = threadIdx.x & 63;
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t v = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); v < n;
        v += waves) {
     const int2 inf = info[v];
-    uint32_t* r = rec + 2 * (size_t)rec_q[v];
-    if (lane == 0) {
-      r[0] = (uint32_t)inf.y;
-      r[1] = (uint32_t)v;
-      if ((inf.y & 1) != 0) r[2 + inf.y] = 0u;  // pad to an even word count
+    uint2* r = rec + rec_q[v];
+    if (lane == 0) r[0] = make_uint2((uint32_t)inf.y, (uint32_t)v);
+    for (int i = lane; i < inf.y; i += 64) {
+      const int32_t u = colidx[(int64_t)inf.x + i];
+      r[1 + i] = make_uint2(rec_q[u], (uint32_t)info[u].y);
     }
-    for (int i = lane; i < inf.y; i += 64) r[2 + i] = rec_q[colidx[(int64_t)inf.x + i]];
   }
 }
 
 // tmp: 2n + 1 int32 of scratch.
-hipError_t launch_build_records(const GraphDev& g, uint32_t* rec_q, uint32_t* rec, int32_t* tmp,
+hipError_t launch_build_records(const GraphDev& g, uint32_t* rec_q, uint2* rec, int32_t* tmp,
                                 uint32_t* tsum, hipStream_t s) {
   const int64_t n = g.n;
   const int64_t tiles = (n + kScanTile - 1) / kScanTile;

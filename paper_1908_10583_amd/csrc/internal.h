@@ -110,10 +110,11 @@ struct GraphDev {
   const int32_t* inhub_node;
   const u64* inhub_base;      // first piece of each, exclusive prefix
   u64 inhub_pieces;           // total pieces
-  // walk records: node v's record starts at 8-byte unit rec_q[v] and holds
-  // the 32-bit words d(v), v, then rec_q of each out-neighbour in CSR order
-  // (padded to an even word count)
-  const uint32_t* rec;
+  // walk records: node v's record starts at 8-byte unit rec_q[v]; unit 0
+  // is the header (d(v), v), then one unit (rec_q[u], d(u)) per out-neighbour
+  // u in CSR order, so a move reads the next node's record start and degree
+  // in one load
+  const uint2* rec;
   const uint32_t* rec_q;
   // rank of each node by out-degree, descending (ties by id): the slot of v
   // in the dense pull-increment rows, and the order of the walk records, so
@@ -229,7 +230,7 @@ hipError_t launch_topk_kth(const float* vals, int kmax, const int32_t* ks, int c
 hipError_t launch_copy_rows(const int32_t* src_ids, const float* src_vals, int kmax,
                             const int32_t* from, const int32_t* to, int count, int32_t* dst_ids,
                             float* dst_vals, hipStream_t s);
-hipError_t launch_build_records(const GraphDev& g, uint32_t* rec_q, uint32_t* rec, int32_t* tmp,
+hipError_t launch_build_records(const GraphDev& g, uint32_t* rec_q, uint2* rec, int32_t* tmp,
                                 uint32_t* tsum, hipStream_t s);
 // rank[v] from the out-degrees; scratch: 4 int32 arrays of n and sort storage
 hipError_t degree_rank_scratch_bytes(int32_t n, size_t* bytes);

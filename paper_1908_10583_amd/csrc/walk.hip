@@ -22,10 +22,10 @@
 // pair per flush instead of one per walk. The sums are integers, so the
 // result is the same either way.
 //
-// Moves read the walk records (GraphDev): one step loads the chosen
-// neighbour's record start from the current record and then that
-// neighbour's 8-byte header (degree, id), so a step on a low-degree node
-// touches one new cache line instead of a node-table line and an edge line.
+// Moves read the walk records (GraphDev): a move loads one 8-byte unit of
+// the current record, which holds the chosen neighbour's record start and
+// out-degree, so each move is one dependent load. The node id is read from
+// the record's header only where the walk stops.
 //
 // Schedule: a persistent grid; each wavefront takes chunks of `chunk`
 // consecutive walk ids from a device work queue and keeps all 64 lanes busy:
@@ -114,7 +114,7 @@ template <bool AGG, bool STORE>
 __global__ __launch_bounds__(kWalkBlock) void k_walks(
     const u64* __restrict__ plan_gi, const u64* __restrict__ plan_off,
     const u64* __restrict__ plan_wfx, Ctrl* ctrl, const QueryDev* __restrict__ Q,
-    QueryStatsDev* QS, const int2* __restrict__ info, const uint32_t* __restrict__ rec,
+    QueryStatsDev* QS, const int2* __restrict__ info, const uint2* __restrict__ rec,
     const uint32_t* __restrict__ rec_q, const u64* __restrict__ idx_off,
     const int32_t* __restrict__ idx_dest, int n, u64* __restrict__ cnt, u64* __restrict__ acc,
     int32_t* __restrict__ store, int chunk) {
@@ -244,6 +244,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
       uint4 y = make_uint4(0u, 0u, 0u, 0u);
       if (!indexed) y = philox4x32_10(make_uint4(v, j, step, 0u), k0, k1);
       if (indexed || (!forced && y.x < ta)) {
+        if (!indexed && step != 0) x = (int32_t)rec[q].y;  // the header's node id
         const size_t t = (size_t)b * n + x;
         if (STORE) {
           store[gid] = x;
@@ -259,13 +260,11 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
         stat_steps += step;
         active = false;
       } else {
-        // the chosen neighbour's record start sits in x's record, usually in
-        // the line its header came from; then the neighbour's header
+        // the chosen neighbour's record start and degree, in one unit
         const uint32_t idx = mul_shift_index(y.y, y.z, deg);
-        q = rec[2 * (size_t)q + 2 + idx];
-        const uint2 h = reinterpret_cast<const uint2*>(rec)[q];
-        deg = h.x;
-        x = (int32_t)h.y;
+        const uint2 u = rec[(size_t)q + 1 + idx];
+        q = u.x;
+        deg = u.y;
         ++step;
         forced = false;
       }
