@@ -25,10 +25,12 @@ if ROOT not in sys.path:
 
 METRIC = "walk-steps/s + SSPPR queries/s (eps=0.5, top-500) vs plain FORA, same GPU"
 PEAK_HBM_GBS = 8000.0
-# algorithmic bytes: per walk move 8 B node header + 4 B neighbour word; per
-# walk 8 B plan read (amortised) + 8 B count + 8 B weight at the end point
+# algorithmic bytes of the method on a CSR graph: per walk move 12 B (the
+# row's two offsets and the chosen column index); per walk 8 B plan read
+# (amortised) + 8 B fixed-point weight at the end point. The bench asks for
+# no per-node walk counts, so no count update is charged.
 BYTES_PER_STEP = 12
-BYTES_PER_WALK = 24
+BYTES_PER_WALK = 16
 
 
 def log(msg):

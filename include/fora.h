@@ -79,7 +79,7 @@ typedef struct fora_query {
   double pf;     /* 0 < pf < 1                                               */
   double rmax;   /* > 0: use this r_max; <= 0: eqn:rmax (section 3.2)        */
   uint64_t seed; /* low 32 bits form the second Philox key word              */
-  uint32_t flags;    /* 0 (Algorithm 2) or FORA_PRUNE_ZERO_HOP | FORA_BALANCE */
+  uint32_t flags;    /* 0 (Algorithm 2) or an OR of the FORA_* flags below  */
   uint32_t reserved; /* 0                                                     */
   double walk_cost;  /* FORA_BALANCE: cost of one walk in residue increments */
 } fora_query;
@@ -103,6 +103,11 @@ typedef struct fora_query {
  * index built for the query's alpha; not combined with
  * FORA_PRUNE_ZERO_HOP. */
 #define FORA_USE_INDEX 4u
+/* Also count the walks that end at each node, into the workspace view
+ * walk_count. A diagnostic: the estimate does not use the counts. Without
+ * the flag those rows stay zero and a walk's end costs one memory-side
+ * atomic instead of two. */
+#define FORA_WALK_COUNTS 8u
 
 #define FORA_MAX_K 4096
 #define FORA_MAX_BATCH 4096
@@ -112,7 +117,8 @@ typedef struct fora_query {
 typedef struct fora_views {
   float *residue;             /* r(s, v), FP32 [batch][n]                     */
   float *reserve;             /* q(s, v), FP32 [batch][n]                     */
-  uint64_t *walk_count;       /* walks ending at v, [batch][n]                */
+  uint64_t *walk_count;       /* walks ending at v, [batch][n]; zero unless
+                                 the query set FORA_WALK_COUNTS            */
   uint64_t *walk_weight_fx;   /* sum of walk weights ending at v, unsigned
                                  fixed point with 62 fraction bits [batch][n] */
   float *pi_hat;              /* q + walk weight, FP32 [batch][n]             */

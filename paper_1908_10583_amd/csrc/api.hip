@@ -98,7 +98,8 @@ int check_query(const fora_graph* g, const fora_query& q) {
   if (!(q.pf > 0.0 && q.pf < 1.0)) return fail(FORA_E_ARG, "pf must be in (0,1)");
   if (q.k < 1 || q.k > n || q.k > FORA_MAX_K) return fail(FORA_E_ARG, "k must be in [1, min(n, FORA_MAX_K)]");
   if (!(q.rmax <= 0.0 || std::isfinite(q.rmax))) return fail(FORA_E_ARG, "rmax must be finite");
-  if ((q.flags & ~(FORA_PRUNE_ZERO_HOP | FORA_BALANCE | FORA_USE_INDEX)) != 0 || q.reserved != 0)
+  if ((q.flags & ~(FORA_PRUNE_ZERO_HOP | FORA_BALANCE | FORA_USE_INDEX | FORA_WALK_COUNTS)) != 0 ||
+      q.reserved != 0)
     return fail(FORA_E_ARG, "unknown query flags");
   if (q.flags & FORA_USE_INDEX) {
     if (!g->idx_dest_owned) return fail(FORA_E_ARG, "FORA_USE_INDEX without an index");
@@ -1096,6 +1097,7 @@ int fora_walk_only(const fora_graph* gc, int64_t entries, const int32_t* d_v,
   qd.key1 = key1;
   qd.alpha = alpha;
   qd.t_alpha = (uint32_t)std::floor(std::ldexp(alpha, 32));
+  qd.flags = FORA_WALK_COUNTS;
   FORA_HIP(hipSetDevice(g->device));
   FORA_HIP(launch_fill_zero((char*)d_ws + c.L.zero_begin, c.L.zero_end - c.L.zero_begin, s));
   FORA_HIP(hipMemcpyAsync(c.w.queries, &qd, sizeof(qd), hipMemcpyHostToDevice, s));

@@ -6,7 +6,8 @@
 // and counter (v, j, s, 0): it stops at the current node x if word 0 is
 // below floor(alpha * 2^32); otherwise it moves to out-neighbour
 // floor(U * d(x) / 2^64) of x, where U = word1 * 2^32 + word2. At its end
-// point t it adds 1 to cnt[t] and its entry's fixed-point weight to acc[t].
+// point t it adds its entry's fixed-point weight to acc[t], and 1 to cnt[t]
+// if the query asked for walk counts (FORA_WALK_COUNTS).
 // With FORA_PRUNE_ZERO_HOP (Algorithm 3) the step-0 block only chooses the
 // first move: every walk starts at a random out-neighbour of v.
 //
@@ -57,14 +58,15 @@ struct AggTable {
 // Adds one end point to the wave's table; false if no slot was found within
 // kAggProbes probes (the caller then adds it to HBM directly). *fresh is set
 // when the key took a new slot.
-__device__ __forceinline__ bool agg_add(const AggTable& t, u64 gi, u64 wfx, bool* fresh) {
+__device__ __forceinline__ bool agg_add(const AggTable& t, u64 gi, u64 wfx, bool count,
+                                        bool* fresh) {
   uint32_t h = (uint32_t)(gi * 0x9E3779B97F4A7C15ull >> 56);  // 8-bit multiplicative hash
   for (int p = 0; p < kAggProbes; ++p) {
     const uint32_t s = (h + (uint32_t)p) & (kAggSlots - 1);
     const u64 old = atomicCAS(&t.key[s], kAggEmpty, gi);
     if (old == kAggEmpty || old == gi) {
       *fresh = old == kAggEmpty;
-      atomicAdd(&t.cnt[s], 1ull);
+      if (count) atomicAdd(&t.cnt[s], 1ull);
       atomicAdd(&t.acc[s], wfx);
       return true;
     }
@@ -79,7 +81,7 @@ __device__ __forceinline__ void agg_flush(const AggTable& t, u64* __restrict__ c
   for (int s = threadIdx.x & 63; s < kAggSlots; s += 64) {
     const u64 k = t.key[s];
     if (k != kAggEmpty) {
-      atomicAdd(&cnt[k], t.cnt[s]);
+      if (t.cnt[s] != 0) atomicAdd(&cnt[k], t.cnt[s]);
       atomicAdd(&acc[k], t.acc[s]);
       t.key[s] = kAggEmpty;
       t.cnt[s] = 0;
@@ -145,6 +147,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
   uint32_t q = 0, deg = 1;  // record start and out-degree of x
   bool forced = false;      // FORA_PRUNE_ZERO_HOP: the next step must move
   bool indexed = false;     // FORA_USE_INDEX: x is the stored end point of the walk
+  bool counts = false;      // FORA_WALK_COUNTS
   u64 gid = 0;              // the walk's global id (STORE)
   u64 wfx = 0;
   int stat_b = -1;
@@ -201,6 +204,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
           k1 = Q[b].key1;
           ta = Q[b].t_alpha;
           forced = (Q[b].flags & FORA_PRUNE_ZERO_HOP) != 0;
+          counts = (Q[b].flags & FORA_WALK_COUNTS) != 0;
           indexed = false;
           if (!STORE && (Q[b].flags & FORA_USE_INDEX)) {
             // walk j of v is stored if j < omega_max(v); later ones run live
@@ -248,8 +252,8 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
         const size_t t = (size_t)b * n + x;
         if (STORE) {
           store[gid] = x;
-        } else if (!AGG || !agg_add(agg, (u64)t, wfx, &fresh)) {
-          atomicAdd(&cnt[t], 1ull);
+        } else if (!AGG || !agg_add(agg, (u64)t, wfx, counts, &fresh)) {
+          if (counts) atomicAdd(&cnt[t], 1ull);
           atomicAdd(&acc[t], wfx);
         }
         if (b != stat_b) {

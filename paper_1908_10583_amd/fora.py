@@ -134,6 +134,7 @@ EXPORTED = ["fora_last_error", "fora_build_csr", "fora_free_graph", "fora_graph_
 FORA_PRUNE_ZERO_HOP = 1
 FORA_BALANCE = 2
 FORA_USE_INDEX = 4
+FORA_WALK_COUNTS = 8
 FORA_MLP_FEATURES = 7
 FORA_MLP_PARAMS = 4751
 FORA_MLP_ACTS = 128
@@ -254,10 +255,19 @@ class Result:
 def fora_ssppr(g: Graph, src: int, alpha: float = 0.2, eps: float = 0.5,
                delta: float | None = None, pf: float | None = None, k: int = 500,
                rmax: float | None = None, seed: int = 0, ws: torch.Tensor | None = None,
-               stats: bool = False, out: tuple | None = None, stream=None) -> Result:
+               stats: bool = False, out: tuple | None = None, stream=None,
+               flags: int = 0) -> Result:
+    """One query. ``flags`` (the FORA_* query flags) need the batch entry
+    point, so a call with flags runs as a batch of one."""
     delta = 1.0 / g.n if delta is None else delta
     pf = 1.0 / g.n if pf is None else pf
     ws = workspace(g, 1) if ws is None else ws
+    if flags:
+        qs = make_queries([src], alpha=alpha, eps=eps, delta=delta, pf=pf, k=k, rmax=rmax,
+                          seed=seed, n=g.n, flags=flags)
+        bout = None if out is None else (out[0].view(1, k), out[1].view(1, k))
+        r = fora_ssppr_batch(g, qs, kmax=k, ws=ws, stats=stats, out=bout, stream=stream)
+        return Result(r.ids[0], r.vals[0], r.stats[0] if stats else None)
     if out is None:
         ids = torch.empty(k, dtype=torch.int32, device=g.device)
         vals = torch.empty(k, dtype=torch.float32, device=g.device)

@@ -59,12 +59,14 @@ class Request:
 
 class Server:
     """S slots over one graph. ``runner``/``ws_size`` can be replaced (host
-    tests drive the scheduler without a GPU)."""
+    tests drive the scheduler without a GPU). ``query_flags`` go into every
+    query (for example FORA_WALK_COUNTS, with ``keep_rows``, to inspect the
+    per-node walk counts)."""
 
     def __init__(self, G, slots: int = 4, max_batch: int = 8, mem_budget: int | None = None,
                  alpha: float = 0.2, delta: float | None = None, pf: float | None = None,
                  model=None, keep_rows: bool = False, stats: bool = False,
-                 ws_size=None, runner=None):
+                 ws_size=None, runner=None, query_flags: int = 0):
         if slots < 1 or max_batch < 1:
             raise ValueError("slots and max_batch must be at least 1")
         self.G = G
@@ -77,6 +79,7 @@ class Server:
         self.model = model
         self.keep_rows = keep_rows
         self.want_stats = stats
+        self.query_flags = int(query_flags)
         self.ws_size = ws_size or (lambda b: fora.fora_workspace_size(G, b))
         if mem_budget is None:
             free, _ = torch.cuda.mem_get_info(G.device)
@@ -193,7 +196,7 @@ class Server:
             qs = fora.make_queries([r.src for r in batch], alpha=self.alpha,
                                    eps=[r.eps for r in batch], delta=self.delta, pf=self.pf,
                                    k=[r.k for r in batch], rmax=self._rmax_for(batch),
-                                   seed=[r.seed for r in batch])
+                                   seed=[r.seed for r in batch], flags=self.query_flags)
             kmax = max(r.k for r in batch)
             res = fora.fora_ssppr_batch(G, qs, kmax=kmax, ws=ws, stats=self.want_stats,
                                         stream=stream)

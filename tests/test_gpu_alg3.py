@@ -55,7 +55,7 @@ def Grmat(grmat):
 
 def _run(G, g, srcs, seeds, flags, rmax=None, walk_cost=0.0, delta=None, pf=None, k=50):
     qs = fora.make_queries(srcs, k=k, seed=seeds, n=g.n, delta=delta, pf=pf, rmax=rmax,
-                           flags=flags, walk_cost=walk_cost)
+                           flags=flags | fora.FORA_WALK_COUNTS, walk_cost=walk_cost)
     ws = fora.workspace(G, len(srcs))
     res = fora.fora_ssppr_batch(G, qs, ws=ws, stats=True)
     rows = {k_: t.cpu().numpy().copy() for k_, t in fora.fora_workspace_views(G, len(srcs), ws).items()}

@@ -20,6 +20,8 @@ if not torch.cuda.is_available():
 from paper_1908_10583_amd import autotune, fora  # noqa: E402
 import walkcmp  # noqa: E402
 
+WC = fora.FORA_WALK_COUNTS  # the tests below compare per-node walk counts
+
 RTOL, ATOL = 1e-5, 1e-12
 
 
@@ -75,7 +77,7 @@ def test_results_do_not_depend_on_tuning(g1k, G1k, shape):
     ref = oracle.fora(g1k, 7, k=50, seed=3)
     G1k.set_tuning(**shape)
     ws = fora.workspace(G1k, 1)
-    res = fora.fora_ssppr(G1k, 7, k=50, seed=3, ws=ws, stats=True)
+    res = fora.fora_ssppr(G1k, 7, k=50, seed=3, ws=ws, stats=True, flags=WC)
     v = _rows(G1k, 1, ws)
     assert res.stats["rounds"] == ref["rounds"]
     assert np.all(close(v["reserve"][0], ref["q"]))
@@ -88,7 +90,7 @@ def test_results_do_not_depend_on_tuning(g1k, G1k, shape):
 
 def test_graph_replays_match_eager(g1k, G1k):
     srcs = [0, 3, 3, 500, 999, 42]
-    qs = fora.make_queries(srcs, k=50, seed=[1, 2, 2, 3, 4, 5], n=g1k.n)
+    qs = fora.make_queries(srcs, k=50, seed=[1, 2, 2, 3, 4, 5], n=g1k.n, flags=WC)
     B = len(srcs)
     ws_e = fora.workspace(G1k, B)
     eager = fora.fora_ssppr_batch(G1k, qs, ws=ws_e, stats=True)
@@ -118,7 +120,7 @@ def test_graph_replays_match_eager(g1k, G1k):
 
 def test_graph_with_too_few_rounds_finishes_on_host(g1k, G1k):
     srcs = [0, 17]
-    qs = fora.make_queries(srcs, k=50, seed=1, n=g1k.n)
+    qs = fora.make_queries(srcs, k=50, seed=1, n=g1k.n, flags=WC)
     ws_e = fora.workspace(G1k, 2)
     eager = fora.fora_ssppr_batch(G1k, qs, ws=ws_e, stats=True)
     ref = _rows(G1k, 2, ws_e)
@@ -137,7 +139,8 @@ def test_mixed_parameters_match_single_calls(g1k, G1k):
     eps = [0.5, 0.3, 0.5, 0.2]
     ks = [10, 50, 1, 200]
     alphas = [0.2, 0.2, 0.15, 0.3]
-    qs = fora.make_queries(srcs, alpha=alphas, eps=eps, k=ks, seed=[0, 1, 2, 3], n=g1k.n)
+    qs = fora.make_queries(srcs, alpha=alphas, eps=eps, k=ks, seed=[0, 1, 2, 3], n=g1k.n,
+                           flags=WC)
     B = len(srcs)
     ws = fora.workspace(G1k, B)
     bat = fora.fora_ssppr_batch(G1k, qs, kmax=200, ws=ws, stats=True)
@@ -145,7 +148,7 @@ def test_mixed_parameters_match_single_calls(g1k, G1k):
     ws1 = fora.workspace(G1k, 1)
     for b in range(B):
         single = fora.fora_ssppr(G1k, srcs[b], alphas[b], eps[b], k=ks[b], seed=b, ws=ws1,
-                                 stats=True)
+                                 stats=True, flags=WC)
         one = _rows(G1k, 1, ws1)
         _same_query(got, one, b, 0, single.stats["omega_unit"])
         assert bat.stats[b]["omega_unit"] == single.stats["omega_unit"]

@@ -59,7 +59,7 @@ def test_index_queries_match_oracle(g1k, G1k, delta):
     # delta = 2e-4 plans 5x more walks than the index holds: the tail runs live
     srcs = [0, 17, 999]
     qs = fora.make_queries(srcs, k=50, seed=[5, 6, 7], n=g1k.n, delta=delta, pf=1e-3,
-                           flags=fora.FORA_USE_INDEX)
+                           flags=fora.FORA_USE_INDEX | fora.FORA_WALK_COUNTS)
     ws = fora.workspace(G1k, len(srcs))
     res = fora.fora_ssppr_batch(G1k, qs, ws=ws, stats=True)
     rows = {k: t.cpu().numpy().copy() for k, t in fora.fora_workspace_views(G1k, 3, ws).items()}
@@ -84,7 +84,8 @@ def test_index_queries_match_oracle(g1k, G1k, delta):
 
 def test_index_and_plain_queries_in_one_batch(g1k, G1k):
     qs = fora.make_queries([0, 0], k=50, seed=[1, 1], n=g1k.n, delta=1e-3, pf=1e-3,
-                           flags=[fora.FORA_USE_INDEX, 0])
+                           flags=[fora.FORA_USE_INDEX | fora.FORA_WALK_COUNTS,
+                                  fora.FORA_WALK_COUNTS])
     ws = fora.workspace(G1k, 2)
     res = fora.fora_ssppr_batch(G1k, qs, ws=ws, stats=True)
     rows = {k: t.cpu().numpy().copy() for k, t in fora.fora_workspace_views(G1k, 2, ws).items()}

@@ -290,7 +290,7 @@ def _e2e(g, G, s, k, seed, rmax=None, eps=0.5):
     ref = oracle.fora(g, s, alpha=ALPHA, eps=eps, k=k, seed=seed, rmax=rmax)
     ws = fora.workspace(G, 1)
     res = fora.fora_ssppr(G, s, alpha=ALPHA, eps=eps, k=k, seed=seed, rmax=rmax, ws=ws,
-                          stats=True)
+                          stats=True, flags=fora.FORA_WALK_COUNTS)
     return ref, res, fora.fora_workspace_views(G, 1, ws)
 
 
@@ -328,6 +328,32 @@ def test_end_to_end_uniform(g1k, G1k, seed):
         assert abs(ref["pi"][t] - kth) <= 2e-5 * kth + 1e-9
 
 
+@pytest.mark.parametrize("agg", [0, 1])
+def test_walk_counts_flag_changes_only_the_counts(g1k, G1k, agg):
+    # the single-query entry point (no counts) against a batch of one that
+    # asks for them: every other output is bit-identical. r_max = 1 (no
+    # push) keeps the walk plan exact: pushed FP32 residues depend on the
+    # order of float atomics, which differs from run to run
+    t0 = G1k.get_tuning()
+    G1k.set_tuning(walk_agg=agg)
+    try:
+        ws_a, ws_b = fora.workspace(G1k, 1), fora.workspace(G1k, 1)
+        a = fora.fora_ssppr(G1k, 3, alpha=ALPHA, k=50, rmax=1.0, seed=8, ws=ws_a, stats=True)
+        b = fora.fora_ssppr(G1k, 3, alpha=ALPHA, k=50, rmax=1.0, seed=8, ws=ws_b, stats=True,
+                            flags=fora.FORA_WALK_COUNTS)
+        va = {k: t[0].cpu().numpy() for k, t in fora.fora_workspace_views(G1k, 1, ws_a).items()}
+        vb = {k: t[0].cpu().numpy() for k, t in fora.fora_workspace_views(G1k, 1, ws_b).items()}
+        assert not va["walk_count"].any()
+        assert int(vb["walk_count"].view(np.uint64).sum()) == b.stats["walks"] > 0
+        for key in ("residue", "reserve", "walk_weight_fx", "pi_hat"):
+            assert np.array_equal(va[key], vb[key]), key
+        assert torch.equal(a.ids, b.ids) and torch.equal(a.vals, b.vals)
+        for key in ("rounds", "walks", "steps", "omega_unit", "rmax"):
+            assert a.stats[key] == b.stats[key], key
+    finally:
+        G1k.set_tuning(**t0)
+
+
 def test_end_to_end_monte_carlo_case(g1k, G1k):
     ref, res, v = _e2e(g1k, G1k, 0, 50, 5, rmax=1.0)
     assert res.stats["rounds"] == 0 and ref["rounds"] == 0
@@ -362,7 +388,7 @@ def test_tiny_graph_self_loop_and_full_k():
 def test_batch_matches_single(g1k, G1k):
     srcs = [0, 5, 5, 999, 123]
     seeds = [1, 2, 2, 3, 4]
-    qs = fora.make_queries(srcs, k=50, seed=seeds, n=g1k.n)
+    qs = fora.make_queries(srcs, k=50, seed=seeds, n=g1k.n, flags=fora.FORA_WALK_COUNTS)
     ws = fora.workspace(G1k, len(srcs))
     out = fora.fora_ssppr_batch(G1k, qs, ws=ws, stats=True)
     vb = fora.fora_workspace_views(G1k, len(srcs), ws)

@@ -31,7 +31,8 @@ def test_results_alone_equal_results_in_the_mix(graph):
     # repeat one request so that a duplicate runs in the mix as well
     trace.append(dict(trace[3], id=24, t=trace[-1]["t"]))
     budget = 2 * fora.fora_workspace_size(G, 4) + fora.fora_workspace_size(G, 2)
-    srv = serve.Server(G, slots=3, max_batch=4, mem_budget=budget, keep_rows=True, stats=True)
+    srv = serve.Server(G, slots=3, max_batch=4, mem_budget=budget, keep_rows=True, stats=True,
+                       query_flags=fora.FORA_WALK_COUNTS)
     reqs = serve.run_trace(srv, trace)
     assert all(r.error is None for r in reqs), [r.error for r in reqs if r.error]
     assert srv.peak <= budget and srv.max_running >= 2
@@ -40,7 +41,7 @@ def test_results_alone_equal_results_in_the_mix(graph):
     same_plan = 0
     for r in reqs:
         alone = fora.fora_ssppr(G, r.src, 0.2, r.eps, 1 / g.n, 1 / g.n, r.k, seed=r.seed,
-                                ws=ws1, stats=True)
+                                ws=ws1, stats=True, flags=fora.FORA_WALK_COUNTS)
         v = {k: t[0].cpu().numpy() for k, t in fora.fora_workspace_views(G, 1, ws1).items()}
         ou = alone.stats["omega_unit"]
         assert r.stats["omega_unit"] == ou and r.stats["rmax"] == alone.stats["rmax"]
