@@ -141,6 +141,12 @@ typedef struct fora_tuning {
                                  this exceed n + m (0: never pull)               */
   int32_t walk_agg;           /* 1: waves sum walk end points in LDS before
                                  adding them to HBM (same results)               */
+  int32_t record_ids;         /* 1 (default): a walk-record slot also holds the
+                                 neighbour's id where record start, degree and
+                                 id fit 64 bits, so no header is read where a
+                                 walk stops; 0: (start, degree) slots only.
+                                 Changing it rebuilds the records (waits for
+                                 the device; same results)                       */
 } fora_tuning;
 
 const char *fora_last_error(void);

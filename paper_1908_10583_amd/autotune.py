@@ -79,8 +79,10 @@ def autotune(G: fora.Graph, queries, path: str | None = None, force: bool = Fals
     ws = fora.workspace(G, B)
     out = (torch.empty((B, kmax), dtype=torch.int32, device=G.device),
            torch.empty((B, kmax), dtype=torch.float32, device=G.device))
+    # record_ids stays 1: ids in the walk-record slots where they fit save a
+    # line read per walk and never cost one
     base = dict(walk_blocks_per_cu=8, walk_chunk=512, push_blocks_per_cu=4, graph_rounds=0,
-                pull_ratio=16)
+                pull_ratio=16, record_ids=1)
     G.set_tuning(**base)
     _timed(G, queries, ws, out, reps=1)  # warm-up
     trials = []

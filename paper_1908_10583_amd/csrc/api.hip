@@ -14,6 +14,7 @@
 // A captured batched pipeline, valid for fixed buffers and shapes.
 struct CapturedGraph {
   int batch = 0, kmax = 0, rounds = 0;
+  bool index_only = false;  // the walk launch shape differs for index-only calls
   void *ws = nullptr, *ids = nullptr, *vals = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -27,7 +28,7 @@ struct fora_graph {
   int32_t* in_colidx_owned = nullptr;
   int32_t* inhub_node_owned = nullptr;
   fora::u64* inhub_base_owned = nullptr;
-  uint2* rec_owned = nullptr;
+  fora::u64* rec_owned = nullptr;
   uint32_t* rec_q_owned = nullptr;
   int32_t* rank_owned = nullptr;
   // FORA+ index
@@ -42,7 +43,7 @@ struct fora_graph {
   std::mutex mu;
   uint64_t* pinned = nullptr;
   std::vector<int> free_slots;
-  fora_tuning tuning{8, 512, 4, 0, fora::kPullRatio, 0};
+  fora_tuning tuning{8, 512, 4, 0, fora::kPullRatio, 0, 1};
   std::mutex graph_mu;
   std::list<CapturedGraph> graphs;  // most recently used first
 };
@@ -171,14 +172,21 @@ struct Call {
   Layout L;
   Ws w;
   int walk_chunk = 0;  // walk ids per work-queue grab for this call
+  bool index_only = false;
 };
 
 // Index walks end at once, so small chunks make the work-queue counter the
-// bottleneck; a call whose queries all read the index grabs larger chunks.
+// bottleneck, and their end points (many at the start node) are all that is
+// left to cost: a call whose queries all read the index grabs larger chunks
+// and always sums end points in LDS first.
 constexpr int kIndexWalkChunk = 32768;
 
 int call_chunk(const fora_graph* g, const Call& c) {
   return c.walk_chunk ? c.walk_chunk : g->tuning.walk_chunk;
+}
+
+bool call_agg(const fora_graph* g, const Call& c) {
+  return c.index_only || g->tuning.walk_agg != 0;
 }
 
 int prepare(const fora_graph* g, int batch, void* d_ws, size_t ws_bytes, Call& c) {
@@ -296,7 +304,7 @@ hipError_t enqueue_pipeline(fora_graph* g, const Call& c, int batch, int rounds,
   if (e == hipSuccess) e = launch_push_gate(c.w, rounds, s);
   if (e == hipSuccess) e = launch_plan(g->dev, c.w, c.L, batch, s);
   if (e == hipSuccess) e = launch_walks(g->dev, c.w, walk_blocks(g), call_chunk(g, c),
-                                 g->tuning.walk_agg != 0, s);
+                                 call_agg(g, c), s);
   if (e == hipSuccess) e = launch_topk(g->dev, c.w, c.L, batch, kmax, d_ids, d_vals, s);
   return e;
 }
@@ -308,7 +316,8 @@ int graph_for(fora_graph* g, const Call& c, int batch, int kmax, void* d_ws, int
   std::lock_guard<std::mutex> lk(g->graph_mu);
   for (auto it = g->graphs.begin(); it != g->graphs.end(); ++it) {
     if (it->batch == batch && it->kmax == kmax && it->rounds == rounds && it->ws == d_ws &&
-        it->ids == (void*)d_ids && it->vals == (void*)d_vals) {
+        it->ids == (void*)d_ids && it->vals == (void*)d_vals &&
+        it->index_only == c.index_only) {
       g->graphs.splice(g->graphs.begin(), g->graphs, it);
       *out = g->graphs.front().exec;
       return FORA_OK;
@@ -318,6 +327,7 @@ int graph_for(fora_graph* g, const Call& c, int batch, int kmax, void* d_ws, int
   cg.batch = batch;
   cg.kmax = kmax;
   cg.rounds = rounds;
+  cg.index_only = c.index_only;
   cg.ws = d_ws;
   cg.ids = d_ids;
   cg.vals = d_vals;
@@ -367,7 +377,7 @@ int run_queries_graph(fora_graph* g, const Call& c, int batch, const std::vector
     if (rc != FORA_OK) return rc;
     FORA_HIP(launch_plan(g->dev, c.w, c.L, batch, s));
     FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), call_chunk(g, c),
-                                 g->tuning.walk_agg != 0, s));
+                                 call_agg(g, c), s));
     FORA_HIP(launch_topk(g->dev, c.w, c.L, batch, kmax, d_ids, d_vals, s));
   }
   return finish(g, c, batch, s, h_stats, qd, nullptr);
@@ -391,6 +401,7 @@ int run_queries(fora_graph* g, int batch, const fora_query* qs, int kmax, void* 
     all_index = all_index && (qs[b].flags & FORA_USE_INDEX);
   }
   c.walk_chunk = all_index ? std::max(walk_chunk(g), kIndexWalkChunk) : walk_chunk(g);
+  c.index_only = all_index;
   FORA_HIP(hipSetDevice(g->device));
   if (g->tuning.graph_rounds > 0)
     return run_queries_graph(g, c, batch, qd, kmax, d_ws, d_ids, d_vals, h_stats, s);
@@ -406,7 +417,7 @@ int run_queries(fora_graph* g, int batch, const fora_query* qs, int kmax, void* 
   FORA_HIP(launch_plan(g->dev, c.w, c.L, batch, s));
   pe.mark(2, s);
   FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), call_chunk(g, c),
-                                 g->tuning.walk_agg != 0, s));
+                                 call_agg(g, c), s));
   pe.mark(3, s);
   FORA_HIP(launch_topk(g->dev, c.w, c.L, batch, kmax, d_ids, d_vals, s));
   pe.mark(4, s);
@@ -442,6 +453,7 @@ Layout make_layout(const GraphDev& g, int32_t batch) {
   L.hist = take(4 * (size_t)kHistBins * batch);
   L.cand_cnt = take(4 * (size_t)batch);
   L.incd = take(4 * cap);
+  L.fbits = take(4 * (size_t)batch * (((size_t)n + 31) / 32));
   L.ecnt = take(8 * 2 * (size_t)kStatSlots * batch);
   L.stop = take(4 * (size_t)batch);
   L.zero_end = align_up(off, 256);
@@ -487,6 +499,7 @@ Ws carve(const Layout& L, void* base) {
   w.hub_idx = (u64*)(p + L.hub_idx);
   w.hub_base = (u64*)(p + L.hub_base);
   w.incd = (float*)(p + L.incd);
+  w.fbits = (uint32_t*)(p + L.fbits);
   w.ecnt = (u64*)(p + L.ecnt);
   w.mode = (int32_t*)(p + L.mode);
   w.pull_list = (int32_t*)(p + L.pull_list);
@@ -614,10 +627,33 @@ int build_rank(fora_graph* g, hipStream_t s) {
 
 // Walk records (one 8-byte header plus one 8-byte unit per out-edge per
 // node); n + m < 2^32 always holds for 32-bit CSR offsets and node ids, so
-// record starts fit 32 bits.
-int build_records(fora_graph* g, hipStream_t s) {
+// record starts fit 32 bits. A slot also carries the neighbour's id when
+// record start, degree and id fit 64 bits together (for example n = 2^20,
+// m = 1.7e7: 25 + 19 + 20 bits).
+int build_records(fora_graph* g, bool with_ids, hipStream_t s) {
   const int64_t n = g->dev.n;
   const int64_t units = g->dev.m + n;
+  int qb = 1, ib = 1;
+  while ((1ll << qb) < units) ++qb;  // record starts are below n + m
+  while ((1ll << ib) < n) ++ib;      // ids are below n
+  const int db = 64 - qb - ib;
+  if (!with_ids) {
+    g->dev.slot_qbits = 32;
+    g->dev.slot_dbits = 32;
+    g->dev.slot_ids = 0;
+  } else if (db >= 1 && db <= 32 && (int64_t)g->dev.max_deg < (1ll << db)) {
+    g->dev.slot_qbits = qb;
+    g->dev.slot_dbits = db;
+    g->dev.slot_ids = 1;
+  } else if (db > 32) {  // small graphs: a 32-bit degree field always fits
+    g->dev.slot_qbits = qb;
+    g->dev.slot_dbits = 32;
+    g->dev.slot_ids = 1;
+  } else {
+    g->dev.slot_qbits = 32;
+    g->dev.slot_dbits = 32;
+    g->dev.slot_ids = 0;
+  }
   const int64_t tiles = (n + 2047) / 2048;
   int32_t* tmp = nullptr;
   uint32_t* tsum = nullptr;
@@ -625,8 +661,9 @@ int build_records(fora_graph* g, hipStream_t s) {
     if (tmp) (void)hipFree(tmp);
     if (tsum) (void)hipFree(tsum);
   };
-  if (hipMalloc(&g->rec_owned, sizeof(uint2) * (size_t)units) != hipSuccess ||
-      hipMalloc(&g->rec_q_owned, sizeof(uint32_t) * ((size_t)n + 1)) != hipSuccess ||
+  if ((!g->rec_owned && hipMalloc(&g->rec_owned, sizeof(u64) * (size_t)units) != hipSuccess) ||
+      (!g->rec_q_owned &&
+       hipMalloc(&g->rec_q_owned, sizeof(uint32_t) * ((size_t)n + 1)) != hipSuccess) ||
       hipMalloc(&tmp, sizeof(int32_t) * (2 * (size_t)n + 1)) != hipSuccess ||
       hipMalloc(&tsum, sizeof(uint32_t) * (size_t)tiles) != hipSuccess) {
     release();
@@ -705,7 +742,7 @@ int fora_build_csr(int32_t n, int64_t m, const int32_t* d_rowptr, const int32_t*
   g->dev.n_hubs = host_flags[2];
   int rrc = build_rank(g, s);
   if (rrc == FORA_OK) rrc = build_reverse(g, s);
-  if (rrc == FORA_OK) rrc = build_records(g, s);
+  if (rrc == FORA_OK) rrc = build_records(g, g->tuning.record_ids != 0, s);
   if (rrc != FORA_OK) {
     const std::string msg = g_err;
     return cleanup(rrc, msg);
@@ -732,7 +769,15 @@ int fora_set_tuning(fora_graph* g, const fora_tuning* t) {
     return fail(FORA_E_ARG, "graph_rounds must be in [0, 4096]");
   if (t->pull_ratio < 0) return fail(FORA_E_ARG, "pull_ratio must be >= 0");
   if (t->walk_agg != 0 && t->walk_agg != 1) return fail(FORA_E_ARG, "walk_agg must be 0 or 1");
+  if (t->record_ids != 0 && t->record_ids != 1)
+    return fail(FORA_E_ARG, "record_ids must be 0 or 1");
   drop_graphs(g);
+  if (t->record_ids != g->tuning.record_ids) {
+    FORA_HIP(hipSetDevice(g->device));
+    FORA_HIP(hipDeviceSynchronize());  // no call may still read the records
+    const int rc = build_records(g, t->record_ids != 0, nullptr);
+    if (rc != FORA_OK) return rc;
+  }
   g->tuning = *t;
   return FORA_OK;
 }
@@ -1104,7 +1149,7 @@ int fora_walk_only(const fora_graph* gc, int64_t entries, const int32_t* d_v,
   if (entries > 0) {
     FORA_HIP(launch_walk_plan_from_host(g->dev, c.w, entries, d_v, d_omega, d_w, s));
     FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), call_chunk(g, c),
-                                 g->tuning.walk_agg != 0, s));
+                                 call_agg(g, c), s));
   }
   std::vector<QueryDev> qv(1, qd);
   fora_stats st{};

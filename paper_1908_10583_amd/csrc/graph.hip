@@ -317,23 +317,26 @@ __global__ void k_rec_start(const int32_t* __restrict__ rank, int32_t n,
 }
 
 __global__ void k_fill_rec(const int2* __restrict__ info, const int32_t* __restrict__ colidx,
-                           int32_t n, const uint32_t* __restrict__ rec_q, uint2* rec) {
+                           int32_t n, const uint32_t* __restrict__ rec_q, u64* rec,
+                           int qbits, int dbits, int ids) {
   const int lane = threadIdx.x & 63;
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t v = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); v < n;
        v += waves) {
     const int2 inf = info[v];
-    uint2* r = rec + rec_q[v];
-    if (lane == 0) r[0] = make_uint2((uint32_t)inf.y, (uint32_t)v);
+    u64* r = rec + rec_q[v];
+    if (lane == 0) r[0] = (u64)(uint32_t)inf.y | ((u64)(uint32_t)v << 32);
     for (int i = lane; i < inf.y; i += 64) {
       const int32_t u = colidx[(int64_t)inf.x + i];
-      r[1 + i] = make_uint2(rec_q[u], (uint32_t)info[u].y);
+      u64 slot = (u64)rec_q[u] | ((u64)(uint32_t)info[u].y << qbits);
+      if (ids) slot |= (u64)(uint32_t)u << (qbits + dbits);
+      r[1 + i] = slot;
     }
   }
 }
 
 // tmp: 2n + 1 int32 of scratch.
-hipError_t launch_build_records(const GraphDev& g, uint32_t* rec_q, uint2* rec, int32_t* tmp,
+hipError_t launch_build_records(const GraphDev& g, uint32_t* rec_q, u64* rec, int32_t* tmp,
                                 uint32_t* tsum, hipStream_t s) {
   const int64_t n = g.n;
   const int64_t tiles = (n + kScanTile - 1) / kScanTile;
@@ -346,7 +349,8 @@ hipError_t launch_build_records(const GraphDev& g, uint32_t* rec_q, uint2* rec, 
   k_tile_apply<<<(unsigned)tiles, 256, 0, s>>>(len, n, tsum, start, len);
   k_rec_start<<<bn, 256, 0, s>>>(g.rank, g.n, (const uint32_t*)start, rec_q);
   const int wb = (int)std::min<int64_t>((n + 3) / 4, 65536);
-  k_fill_rec<<<wb, 256, 0, s>>>(g.info, g.colidx, g.n, rec_q, rec);
+  k_fill_rec<<<wb, 256, 0, s>>>(g.info, g.colidx, g.n, rec_q, rec, g.slot_qbits, g.slot_dbits,
+                                g.slot_ids);
   return hipGetLastError();
 }
 

@@ -111,11 +111,17 @@ struct GraphDev {
   const u64* inhub_base;      // first piece of each, exclusive prefix
   u64 inhub_pieces;           // total pieces
   // walk records: node v's record starts at 8-byte unit rec_q[v]; unit 0
-  // is the header (d(v), v), then one unit (rec_q[u], d(u)) per out-neighbour
-  // u in CSR order, so a move reads the next node's record start and degree
-  // in one load
-  const uint2* rec;
+  // is the header d(v) | v << 32, then one unit per out-neighbour u in CSR
+  // order holding rec_q[u] in bits [0, slot_qbits) and d(u) in the next
+  // slot_dbits bits, so a move reads the next node's record start and degree
+  // in one load. With slot_ids, u itself sits in the bits above them and the
+  // header is never read; otherwise the fields are 32 bits each and a walk
+  // reads its end node's id from the header.
+  const u64* rec;
   const uint32_t* rec_q;
+  int32_t slot_qbits;
+  int32_t slot_dbits;
+  int32_t slot_ids;
   // rank of each node by out-degree, descending (ties by id): the slot of v
   // in the dense pull-increment rows, and the order of the walk records, so
   // that the values read most often (those of high-degree nodes) share lines
@@ -127,7 +133,7 @@ struct GraphDev {
 
 struct Layout {
   size_t ctrl, qstats, queries, r, q, cnt, acc, pi;
-  size_t fr0, fr1, frx, hub_idx, hub_base, incd, ecnt, mode, pull_list, stop;
+  size_t fr0, fr1, frx, hub_idx, hub_base, incd, fbits, ecnt, mode, pull_list, stop;
   size_t plan_gi, plan_off, plan_wfx;
   size_t tile_cnt, tile_walks, tile_eoff, tile_woff;
   size_t hist, sel, cand_key, cand_id, cand_cnt, blk_ties;
@@ -152,6 +158,7 @@ struct Ws {
   u64* hub_idx;   // frontier index of each split entry
   u64* hub_base;  // first piece number of each split entry
   float* incd;    // [batch][n]: frontier increments, dense, for pull rounds
+  uint32_t* fbits;  // [batch][ceil(n / 32)]: the frontier as bits, by degree rank
   u64* ecnt;      // [2][batch][kStatSlots]: frontier edges per query, by round parity
   int32_t* mode;  // [batch]: 1 if the query's current round pulls
   int32_t* pull_list;  // queries in pull mode this round
@@ -230,7 +237,7 @@ hipError_t launch_topk_kth(const float* vals, int kmax, const int32_t* ks, int c
 hipError_t launch_copy_rows(const int32_t* src_ids, const float* src_vals, int kmax,
                             const int32_t* from, const int32_t* to, int count, int32_t* dst_ids,
                             float* dst_vals, hipStream_t s);
-hipError_t launch_build_records(const GraphDev& g, uint32_t* rec_q, uint2* rec, int32_t* tmp,
+hipError_t launch_build_records(const GraphDev& g, uint32_t* rec_q, u64* rec, int32_t* tmp,
                                 uint32_t* tsum, hipStream_t s);
 // rank[v] from the out-degrees; scratch: 4 int32 arrays of n and sort storage
 hipError_t degree_rank_scratch_bytes(int32_t n, size_t* bytes);

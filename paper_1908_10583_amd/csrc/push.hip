@@ -20,7 +20,9 @@
 //   accumulation, no atomics to HBM), then updates r(u) once and tests it.
 //   The dense increments sit at each node's degree rank (GraphDev::rank),
 //   and the reverse graph stores in-neighbours by rank, so the gathers of
-//   high-degree nodes' increments (the most frequent ones) share lines.
+//   high-degree nodes' increments (the most frequent ones) share lines. A
+//   bit per rank marks the frontier (n / 8 bytes per query, which stays in
+//   L2), so only in-neighbours in the frontier have their increment read.
 //   Nodes of in-degree above kHubDeg are summed in pieces by any block and
 //   added with one atomic per piece.
 #include "internal.h"
@@ -65,7 +67,8 @@ hipError_t launch_init_queries(const GraphDev& g, const Ws& w, int batch, hipStr
 __global__ __launch_bounds__(256) void k_push_snapshot(
     int t, Ctrl* ctrl, const u64* __restrict__ fr_in, float* __restrict__ frx,
     float* __restrict__ r, float* __restrict__ q, float* __restrict__ incd,
-    const QueryDev* __restrict__ Q, StatSlot* slots, u64* ecnt, const int2* __restrict__ info,
+    uint32_t* __restrict__ fbits, const QueryDev* __restrict__ Q, StatSlot* slots, u64* ecnt,
+    const int2* __restrict__ info,
     const int32_t* __restrict__ rank, const int32_t* __restrict__ stop, int n, int batch,
     int32_t* frontier_log, int64_t log_cap, u64 cap, u64* hub_idx,
     u64* hub_base, u64 hub_cap) {
@@ -100,7 +103,9 @@ __global__ __launch_bounds__(256) void k_push_snapshot(
     const int d = info[v].y;
     const float inc = (float)(((1.0 - alpha) * (double)x) / (double)d);
     frx[i] = inc;
-    incd[(size_t)b * n + rank[v]] = inc;
+    const int32_t rk = rank[v];
+    incd[(size_t)b * n + rk] = inc;
+    atomicOr(&fbits[(size_t)b * (((size_t)n + 31) >> 5) + (rk >> 5)], 1u << (rk & 31));
     if (d > kHubDeg) {
       const u64 pieces = (u64)((d + kHubPiece - 1) / kHubPiece);
       const u64 old = atomicAdd(&ctrl->hub_ctr[t & 1], (1ull << 40) | pieces);
@@ -230,8 +235,9 @@ __device__ __forceinline__ void push_edge(int b, int u, float inc, double rmax,
 
 __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
     int t, Ctrl* ctrl, u64* __restrict__ fr_out, u64 cap, float* __restrict__ r,
-    const float* __restrict__ incd, const QueryDev* __restrict__ Q,
-    const int32_t* __restrict__ pull_list, const int2* __restrict__ info,
+    const float* __restrict__ incd, const uint32_t* __restrict__ fbits,
+    const QueryDev* __restrict__ Q, const int32_t* __restrict__ pull_list,
+    const int2* __restrict__ info,
     const int32_t* __restrict__ in_rowptr, const int32_t* __restrict__ in_colidx,
     const int32_t* __restrict__ inhub_node, const u64* __restrict__ inhub_base, int n_inhubs,
     u64 inhub_pieces, int n) {
@@ -257,6 +263,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
     const u64 j = it % per_query;
     const double rmax = Q[b].rmax;
     const float* inc_row = incd + (size_t)b * n;
+    const uint32_t* fb_row = fbits + (size_t)b * (((size_t)n + 31) >> 5);
     if (j < chunks) {
       const int u0 = (int)(j * kScatterBlock);
       const int u = u0 + (int)threadIdx.x;
@@ -279,8 +286,11 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
           if (s_pre[mid] <= k) lo = mid;
           else hi = mid - 1;
         }
-        const float val = inc_row[in_colidx[(int64_t)s_start[lo] + (int64_t)(k - s_pre[lo])]];
-        if (val != 0.0f) atomicAdd(&s_sum[lo], val);
+        const int32_t w = in_colidx[(int64_t)s_start[lo] + (int64_t)(k - s_pre[lo])];
+        if ((fb_row[w >> 5] >> (w & 31)) & 1u) {
+          const float val = inc_row[w];
+          if (val != 0.0f) atomicAdd(&s_sum[lo], val);
+        }
       }
       __syncthreads();
       if (u < n) {
@@ -306,8 +316,10 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
       const int64_t first = a + (int64_t)(p - inhub_base[lo]) * kHubPiece;
       const int64_t end = first + kHubPiece < c ? first + kHubPiece : c;
       float part = 0.0f;
-      for (int64_t k = first + threadIdx.x; k < end; k += kScatterBlock)
-        part += inc_row[in_colidx[k]];
+      for (int64_t k = first + threadIdx.x; k < end; k += kScatterBlock) {
+        const int32_t w = in_colidx[k];
+        if ((fb_row[w >> 5] >> (w & 31)) & 1u) part += inc_row[w];
+      }
       const float sum = block_sum(part, s_tmpf);
       if (threadIdx.x == 0 && sum > 0.0f) {
         const size_t gi = (size_t)b * n + u;
@@ -329,6 +341,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
 __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
     int t, Ctrl* ctrl, const u64* __restrict__ fr_in, const float* __restrict__ frx,
     u64* __restrict__ fr_out, u64 cap, float* __restrict__ r, float* __restrict__ incd,
+    uint32_t* __restrict__ fbits,
     const int32_t* __restrict__ mode, const int32_t* __restrict__ stop,
     const QueryDev* __restrict__ Q, const int2* __restrict__ info,
     const int32_t* __restrict__ colidx, const int32_t* __restrict__ rank, int n,
@@ -355,11 +368,17 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
   }
   const NextQueue nq{s_queue, &s_qn, &s_qbase, &ctrl->fr_cnt[(t + 1) & 1], fr_out, cap, ctrl};
   if (threadIdx.x == 0) s_qn = 0;
-  // the dense increments were read by the pull launch; clear them
+  // the dense increments and frontier bits were read by the pull launch;
+  // clear them (a bit word holds only this round's frontier, so whole words
+  // are zeroed)
+  const size_t nw = ((size_t)n + 31) >> 5;
   for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
        i += (u64)gridDim.x * blockDim.x) {
     const u64 e = fr_in[i];
-    incd[(size_t)(e >> 32) * n + rank[(uint32_t)e]] = 0.0f;
+    const size_t b = (size_t)(e >> 32);
+    const int32_t rk = rank[(uint32_t)e];
+    incd[b * n + rk] = 0.0f;
+    fbits[b * nw + (rk >> 5)] = 0u;
   }
   __syncthreads();
 
@@ -477,18 +496,19 @@ hipError_t launch_push_round(const GraphDev& g, const Ws& w, const Layout& L, in
   const size_t smem = (size_t)batch * (sizeof(u64) + sizeof(uint32_t));
   const u64 cap = (u64)L.cap;
   k_push_snapshot<<<blocks, 256, smem, s>>>(t, w.ctrl, w.fr[par], w.frx, w.r, w.q, w.incd,
-                                            w.queries, w.qstats, w.ecnt, g.info, g.rank, w.stop,
+                                            w.fbits, w.queries, w.qstats, w.ecnt, g.info, g.rank, w.stop,
                                             g.n, batch,
                                             frontier_log, log_cap, cap, w.hub_idx, w.hub_base,
                                             (u64)L.hub_cap);
   k_push_mode<<<1, 256, 0, s>>>(t, w.ctrl, w.ecnt, w.mode, w.pull_list, w.qstats, w.queries,
                                 w.stop, batch, (u64)g.n + (u64)g.m, pull_ratio);
   k_push_pull<<<blocks, kScatterBlock, 0, s>>>(t, w.ctrl, w.fr[par ^ 1], cap, w.r, w.incd,
-                                               w.queries, w.pull_list, g.info, g.in_rowptr,
+                                               w.fbits, w.queries, w.pull_list, g.info, g.in_rowptr,
                                                g.in_colidx, g.inhub_node, g.inhub_base,
                                                g.n_inhubs, g.inhub_pieces, g.n);
   k_push_scatter<<<blocks, kScatterBlock, 0, s>>>(t, w.ctrl, w.fr[par], w.frx, w.fr[par ^ 1],
-                                                  cap, w.r, w.incd, w.mode, w.stop, w.queries,
+                                                  cap, w.r, w.incd, w.fbits, w.mode, w.stop,
+                                                  w.queries,
                                                   g.info, g.colidx, g.rank, g.n, w.hub_idx,
                                                   w.hub_base,
                                                   (u64)L.hub_cap);

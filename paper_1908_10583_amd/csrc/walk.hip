@@ -25,8 +25,9 @@
 //
 // Moves read the walk records (GraphDev): a move loads one 8-byte unit of
 // the current record, which holds the chosen neighbour's record start and
-// out-degree, so each move is one dependent load. The node id is read from
-// the record's header only where the walk stops.
+// out-degree (and its id, where the graph's sizes let the three fit), so
+// each move is one dependent load. Without ids in the slots, the end node's
+// id is read from its record's header where the walk stops.
 //
 // Schedule: a persistent grid; each wavefront takes chunks of `chunk`
 // consecutive walk ids from a device work queue and keeps all 64 lanes busy:
@@ -116,10 +117,10 @@ template <bool AGG, bool STORE>
 __global__ __launch_bounds__(kWalkBlock) void k_walks(
     const u64* __restrict__ plan_gi, const u64* __restrict__ plan_off,
     const u64* __restrict__ plan_wfx, Ctrl* ctrl, const QueryDev* __restrict__ Q,
-    QueryStatsDev* QS, const int2* __restrict__ info, const uint2* __restrict__ rec,
-    const uint32_t* __restrict__ rec_q, const u64* __restrict__ idx_off,
-    const int32_t* __restrict__ idx_dest, int n, u64* __restrict__ cnt, u64* __restrict__ acc,
-    int32_t* __restrict__ store, int chunk) {
+    QueryStatsDev* QS, const int2* __restrict__ info, const u64* __restrict__ rec,
+    const uint32_t* __restrict__ rec_q, int qbits, int dbits, int slot_ids,
+    const u64* __restrict__ idx_off, const int32_t* __restrict__ idx_dest, int n,
+    u64* __restrict__ cnt, u64* __restrict__ acc, int32_t* __restrict__ store, int chunk) {
   __shared__ u64 s_agg[AGG ? 3 * kWalkWaves * kAggSlots : 1];
   if (ctrl->error || ctrl->skip) return;
   const u64 W = ctrl->walks;
@@ -127,6 +128,9 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
   const u64 nchunks = (W + chunk - 1) / (u64)chunk;
   const int lane = threadIdx.x & 63;
   const int slot = (int)(((blockIdx.x << 2) + (threadIdx.x >> 6)) & (kStatSlots - 1));
+  const u64 qmask = (1ull << qbits) - 1;  // qbits <= 32, dbits <= 32
+  const u64 dmask = (1ull << dbits) - 1;
+  const int ishift = qbits + dbits;        // < 64 where slot_ids is set
 
   AggTable agg{};
   unsigned agg_fill = 0;  // wave-uniform count of keys in the table
@@ -248,7 +252,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
       uint4 y = make_uint4(0u, 0u, 0u, 0u);
       if (!indexed) y = philox4x32_10(make_uint4(v, j, step, 0u), k0, k1);
       if (indexed || (!forced && y.x < ta)) {
-        if (!indexed && step != 0) x = (int32_t)rec[q].y;  // the header's node id
+        if (!indexed && step != 0 && !slot_ids) x = (int32_t)(rec[q] >> 32);  // header's id
         const size_t t = (size_t)b * n + x;
         if (STORE) {
           store[gid] = x;
@@ -264,11 +268,12 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
         stat_steps += step;
         active = false;
       } else {
-        // the chosen neighbour's record start and degree, in one unit
+        // the chosen neighbour's record start and degree (and id), in one unit
         const uint32_t idx = mul_shift_index(y.y, y.z, deg);
-        const uint2 u = rec[(size_t)q + 1 + idx];
-        q = u.x;
-        deg = u.y;
+        const u64 u = rec[(size_t)q + 1 + idx];
+        q = (uint32_t)(u & qmask);
+        deg = (uint32_t)((u >> qbits) & dmask);
+        if (slot_ids) x = (int32_t)(u >> ishift);
         ++step;
         forced = false;
       }
@@ -290,11 +295,11 @@ hipError_t launch_walks(const GraphDev& g, const Ws& w, int blocks, int chunk, b
   if (agg)
     k_walks<true, false><<<blocks, kWalkBlock, 0, s>>>(
         w.plan_gi, w.plan_off, w.plan_wfx, w.ctrl, w.queries, w.qstats, g.info, g.rec, g.rec_q,
-        g.idx_off, g.idx_dest, g.n, w.cnt, w.acc, nullptr, chunk);
+        g.slot_qbits, g.slot_dbits, g.slot_ids, g.idx_off, g.idx_dest, g.n, w.cnt, w.acc, nullptr, chunk);
   else
     k_walks<false, false><<<blocks, kWalkBlock, 0, s>>>(
         w.plan_gi, w.plan_off, w.plan_wfx, w.ctrl, w.queries, w.qstats, g.info, g.rec, g.rec_q,
-        g.idx_off, g.idx_dest, g.n, w.cnt, w.acc, nullptr, chunk);
+        g.slot_qbits, g.slot_dbits, g.slot_ids, g.idx_off, g.idx_dest, g.n, w.cnt, w.acc, nullptr, chunk);
   return hipGetLastError();
 }
 
@@ -304,7 +309,8 @@ hipError_t launch_index_walks(const GraphDev& g, const u64* plan_gi, const u64* 
                               const QueryDev* Q, QueryStatsDev* QS, int32_t* dest, int blocks,
                               int chunk, hipStream_t s) {
   k_walks<false, true><<<blocks, kWalkBlock, 0, s>>>(plan_gi, off, nullptr, ctrl, Q, QS, g.info,
-                                                     g.rec, g.rec_q, nullptr, nullptr, g.n,
+                                                     g.rec, g.rec_q, g.slot_qbits, g.slot_dbits,
+                                                     g.slot_ids, nullptr, nullptr, g.n,
                                                      nullptr, nullptr, dest, chunk);
   return hipGetLastError();
 }

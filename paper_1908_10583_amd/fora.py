@@ -54,7 +54,8 @@ class fora_query(ctypes.Structure):
 class fora_tuning(ctypes.Structure):
     _fields_ = [("walk_blocks_per_cu", ctypes.c_int32), ("walk_chunk", ctypes.c_int32),
                 ("push_blocks_per_cu", ctypes.c_int32), ("graph_rounds", ctypes.c_int32),
-                ("pull_ratio", ctypes.c_int32), ("walk_agg", ctypes.c_int32)]
+                ("pull_ratio", ctypes.c_int32), ("walk_agg", ctypes.c_int32),
+                ("record_ids", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
