@@ -452,8 +452,7 @@ Layout make_layout(const GraphDev& g, int32_t batch) {
   L.acc = take(8 * cap);
   L.hist = take(4 * (size_t)kHistBins * batch);
   L.cand_cnt = take(4 * (size_t)batch);
-  L.incd = take(4 * cap);
-  L.fbits = take(4 * (size_t)batch * (((size_t)n + 31) / 32));
+  L.incd = take(4 * (((size_t)batch + 3) / 4 * 4) * (size_t)n);
   L.ecnt = take(8 * 2 * (size_t)kStatSlots * batch);
   L.stop = take(4 * (size_t)batch);
   L.zero_end = align_up(off, 256);
@@ -499,7 +498,6 @@ Ws carve(const Layout& L, void* base) {
   w.hub_idx = (u64*)(p + L.hub_idx);
   w.hub_base = (u64*)(p + L.hub_base);
   w.incd = (float*)(p + L.incd);
-  w.fbits = (uint32_t*)(p + L.fbits);
   w.ecnt = (u64*)(p + L.ecnt);
   w.mode = (int32_t*)(p + L.mode);
   w.pull_list = (int32_t*)(p + L.pull_list);

@@ -90,7 +90,7 @@ struct Ctrl {
   u64 hub_ctr[2];      // split frontier entries: (count << 40) | pieces, by round parity
   int32_t error;
   int32_t skip;        // set by the graph's gate when the push needs more rounds
-  int32_t npull;       // queries whose current round runs in pull mode
+  int32_t npull;       // entries of the pull list (query groups) this round
   int32_t pad2;
   u64 round_size[kMaxRoundsLogged];
 };
@@ -133,7 +133,7 @@ struct GraphDev {
 
 struct Layout {
   size_t ctrl, qstats, queries, r, q, cnt, acc, pi;
-  size_t fr0, fr1, frx, hub_idx, hub_base, incd, fbits, ecnt, mode, pull_list, stop;
+  size_t fr0, fr1, frx, hub_idx, hub_base, incd, ecnt, mode, pull_list, stop;
   size_t plan_gi, plan_off, plan_wfx;
   size_t tile_cnt, tile_walks, tile_eoff, tile_woff;
   size_t hist, sel, cand_key, cand_id, cand_cnt, blk_ties;
@@ -157,11 +157,12 @@ struct Ws {
   float* frx;
   u64* hub_idx;   // frontier index of each split entry
   u64* hub_base;  // first piece number of each split entry
-  float* incd;    // [batch][n]: frontier increments, dense, for pull rounds
-  uint32_t* fbits;  // [batch][ceil(n / 32)]: the frontier as bits, by degree rank
+  float* incd;    // [ceil(batch / 4)][n][4]: frontier increments by degree rank, four
+                  // queries per node unit, dense, for pull rounds
   u64* ecnt;      // [2][batch][kStatSlots]: frontier edges per query, by round parity
   int32_t* mode;  // [batch]: 1 if the query's current round pulls
-  int32_t* pull_list;  // queries in pull mode this round
+  int32_t* pull_list;  // groups of 4 queries with one in pull mode this round:
+                       // group << 4 | mask of the pulling members
   int32_t* stop;       // [batch]: 0, or 1 + the first round the balance rule skips
   u64* plan_gi;
   u64* plan_off;

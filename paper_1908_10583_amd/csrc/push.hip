@@ -20,9 +20,11 @@
 //   accumulation, no atomics to HBM), then updates r(u) once and tests it.
 //   The dense increments sit at each node's degree rank (GraphDev::rank),
 //   and the reverse graph stores in-neighbours by rank, so the gathers of
-//   high-degree nodes' increments (the most frequent ones) share lines. A
-//   bit per rank marks the frontier (n / 8 bytes per query, which stays in
-//   L2), so only in-neighbours in the frontier have their increment read.
+//   high-degree nodes' increments (the most frequent ones) share lines.
+//   Queries are taken in groups of four, whose increments for one node form
+//   one 16-byte unit: a pull reads each in-edge's source once per group
+//   (one load), so the random reads per in-edge do not grow with the
+//   number of pulling queries.
 //   Nodes of in-degree above kHubDeg are summed in pieces by any block and
 //   added with one atomic per piece.
 #include "internal.h"
@@ -31,6 +33,12 @@
 namespace fora {
 
 constexpr int kScatterBlock = 256;
+constexpr int kPullGroup = 4;  // queries per increment unit
+
+// Position of query b's increment for the node of degree rank rk.
+__device__ __forceinline__ size_t incd_index(int b, int32_t rk, int n) {
+  return ((size_t)(b >> 2) * (size_t)n + (size_t)rk) * kPullGroup + (size_t)(b & 3);
+}
 constexpr unsigned kQueueCap = 1024;  // LDS-staged next-frontier entries per block
 
 // FORA_BALANCE before round 0 (nothing pushed): stop at once iff the
@@ -67,8 +75,7 @@ hipError_t launch_init_queries(const GraphDev& g, const Ws& w, int batch, hipStr
 __global__ __launch_bounds__(256) void k_push_snapshot(
     int t, Ctrl* ctrl, const u64* __restrict__ fr_in, float* __restrict__ frx,
     float* __restrict__ r, float* __restrict__ q, float* __restrict__ incd,
-    uint32_t* __restrict__ fbits, const QueryDev* __restrict__ Q, StatSlot* slots, u64* ecnt,
-    const int2* __restrict__ info,
+    const QueryDev* __restrict__ Q, StatSlot* slots, u64* ecnt, const int2* __restrict__ info,
     const int32_t* __restrict__ rank, const int32_t* __restrict__ stop, int n, int batch,
     int32_t* frontier_log, int64_t log_cap, u64 cap, u64* hub_idx,
     u64* hub_base, u64 hub_cap) {
@@ -103,9 +110,7 @@ __global__ __launch_bounds__(256) void k_push_snapshot(
     const int d = info[v].y;
     const float inc = (float)(((1.0 - alpha) * (double)x) / (double)d);
     frx[i] = inc;
-    const int32_t rk = rank[v];
-    incd[(size_t)b * n + rk] = inc;
-    atomicOr(&fbits[(size_t)b * (((size_t)n + 31) >> 5) + (rk >> 5)], 1u << (rk & 31));
+    incd[incd_index(b, rank[v], n)] = inc;
     if (d > kHubDeg) {
       const u64 pieces = (u64)((d + kHubPiece - 1) / kHubPiece);
       const u64 old = atomicAdd(&ctrl->hub_ctr[t & 1], (1ull << 40) | pieces);
@@ -139,8 +144,9 @@ __global__ __launch_bounds__(256) void k_push_snapshot(
   }
 }
 
-// One block: choose pull or push for every query's round t; list the pull
-// queries; clear the next round's frontier-edge slots.
+// One block: choose pull or push for every query's round t; list the
+// groups of four queries with a pulling member; clear the next round's
+// frontier-edge slots.
 __global__ __launch_bounds__(256) void k_push_mode(int t, Ctrl* ctrl, u64* ecnt, int32_t* mode,
                                                    int32_t* pull_list, StatSlot* slots,
                                                    const QueryDev* __restrict__ Q,
@@ -173,9 +179,14 @@ __global__ __launch_bounds__(256) void k_push_mode(int t, Ctrl* ctrl, u64* ecnt,
         }
       }
     }
+    // lanes 4k..4k+3 of a wave hold one group (base is a multiple of 256)
+    const unsigned lane = threadIdx.x & 63;
+    const u64 bal = __ballot(pull != 0);
+    const int32_t gmask = (int32_t)((bal >> (lane & ~3u)) & 0xFull);
+    const int32_t lead = ((lane & 3u) == 0 && gmask != 0) ? 1 : 0;
     int32_t tot;
-    const int32_t pos = carry + block_exclusive_scan(pull, s_tmp, tot);
-    if (pull) pull_list[pos] = b;
+    const int32_t pos = carry + block_exclusive_scan(lead, s_tmp, tot);
+    if (lead) pull_list[pos] = ((b >> 2) << 4) | gmask;
     carry += tot;
   }
   for (size_t i = threadIdx.x; i < (size_t)batch * kStatSlots; i += 256) ec_next[i] = 0;
@@ -233,38 +244,45 @@ __device__ __forceinline__ void push_edge(int b, int u, float inc, double rmax,
   }
 }
 
+// Items: (chunk of kScatterBlock destination nodes, pull group), then
+// (piece of a high-in-degree node, pull group). A chunk item scans the
+// chunk's in-degrees, finds each in-edge's owner, and reads the source's
+// four increments with one 16-byte load; each pulling member of the group
+// sums its own increment into its LDS row.
 __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
     int t, Ctrl* ctrl, u64* __restrict__ fr_out, u64 cap, float* __restrict__ r,
-    const float* __restrict__ incd, const uint32_t* __restrict__ fbits,
-    const QueryDev* __restrict__ Q, const int32_t* __restrict__ pull_list,
-    const int2* __restrict__ info,
+    const float* __restrict__ incd, const QueryDev* __restrict__ Q,
+    const int32_t* __restrict__ pull_list, const int2* __restrict__ info,
     const int32_t* __restrict__ in_rowptr, const int32_t* __restrict__ in_colidx,
     const int32_t* __restrict__ inhub_node, const u64* __restrict__ inhub_base, int n_inhubs,
     u64 inhub_pieces, int n) {
   __shared__ u64 s_pre[kScatterBlock];
   __shared__ int32_t s_start[kScatterBlock];
-  __shared__ float s_sum[kScatterBlock];
+  __shared__ float s_sum[kPullGroup][kScatterBlock];
   __shared__ u64 s_queue[kQueueCap];
   __shared__ unsigned s_qn;
   __shared__ u64 s_qbase;
   __shared__ u64 s_tmp[kScatterBlock / 64];
   __shared__ float s_tmpf[kScatterBlock / 64];
   (void)t;
-  const int npull = ctrl->npull;
-  if (npull == 0) return;  // uniform
+  const int ngroups = ctrl->npull;
+  if (ngroups == 0) return;  // uniform
   const NextQueue nq{s_queue, &s_qn, &s_qbase, &ctrl->fr_cnt[(t + 1) & 1], fr_out, cap, ctrl};
   if (threadIdx.x == 0) s_qn = 0;
   __syncthreads();
+  const float4* inc4 = reinterpret_cast<const float4*>(incd);
   const u64 chunks = ((u64)n + kScatterBlock - 1) / kScatterBlock;
-  const u64 per_query = chunks + inhub_pieces;
-  const u64 items = per_query * (u64)npull;
+  const u64 chunk_items = chunks * (u64)ngroups;
+  const u64 items = chunk_items + inhub_pieces * (u64)ngroups;
   for (u64 it = blockIdx.x; it < items; it += gridDim.x) {
-    const int b = pull_list[it / per_query];
-    const u64 j = it % per_query;
-    const double rmax = Q[b].rmax;
-    const float* inc_row = incd + (size_t)b * n;
-    const uint32_t* fb_row = fbits + (size_t)b * (((size_t)n + 31) >> 5);
-    if (j < chunks) {
+    const bool is_chunk = it < chunk_items;
+    const u64 gidx = is_chunk ? it / chunks : (it - chunk_items) / inhub_pieces;
+    const int32_t entry = pull_list[gidx];
+    const int grp = entry >> 4;
+    const unsigned mask = (unsigned)entry & 15u;
+    const float4* grow = inc4 + (size_t)grp * n;
+    if (is_chunk) {
+      const u64 j = it % chunks;
       const int u0 = (int)(j * kScatterBlock);
       const int u = u0 + (int)threadIdx.x;
       u64 deg = 0;
@@ -273,7 +291,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
         s_start[threadIdx.x] = a;
         deg = (c - a) > kHubDeg ? 0ull : (u64)(c - a);
       }
-      s_sum[threadIdx.x] = 0.0f;
+      for (int g = 0; g < kPullGroup; ++g) s_sum[g][threadIdx.x] = 0.0f;
       u64 total;
       const u64 pre = block_exclusive_scan(deg, s_tmp, total);
       s_pre[threadIdx.x] = pre;
@@ -286,25 +304,29 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
           if (s_pre[mid] <= k) lo = mid;
           else hi = mid - 1;
         }
-        const int32_t w = in_colidx[(int64_t)s_start[lo] + (int64_t)(k - s_pre[lo])];
-        if ((fb_row[w >> 5] >> (w & 31)) & 1u) {
-          const float val = inc_row[w];
-          if (val != 0.0f) atomicAdd(&s_sum[lo], val);
-        }
+        const float4 v = grow[in_colidx[(int64_t)s_start[lo] + (int64_t)(k - s_pre[lo])]];
+        if ((mask & 1u) && v.x != 0.0f) atomicAdd(&s_sum[0][lo], v.x);
+        if ((mask & 2u) && v.y != 0.0f) atomicAdd(&s_sum[1][lo], v.y);
+        if ((mask & 4u) && v.z != 0.0f) atomicAdd(&s_sum[2][lo], v.z);
+        if ((mask & 8u) && v.w != 0.0f) atomicAdd(&s_sum[3][lo], v.w);
       }
       __syncthreads();
       if (u < n) {
-        const float add = s_sum[threadIdx.x];
-        if (add > 0.0f) {
-          const size_t gi = (size_t)b * n + u;
-          const float now = r[gi] + add;
-          r[gi] = now;
-          if ((double)now > rmax * (double)info[u].y) nq.push(((u64)b << 32) | (uint32_t)u);
+        const double d_u = (double)info[u].y;
+        for (int g = 0; g < kPullGroup; ++g) {
+          const float add = s_sum[g][threadIdx.x];
+          if (((mask >> g) & 1u) && add > 0.0f) {
+            const int b = grp * kPullGroup + g;
+            const size_t gi = (size_t)b * n + u;
+            const float now = r[gi] + add;
+            r[gi] = now;
+            if ((double)now > Q[b].rmax * d_u) nq.push(((u64)b << 32) | (uint32_t)u);
+          }
         }
       }
     } else {
       // a piece of a node with large in-degree
-      const u64 p = j - chunks;
+      const u64 p = (it - chunk_items) % inhub_pieces;
       int lo = 0, hi = n_inhubs - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -315,18 +337,30 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
       const int64_t a = in_rowptr[u], c = in_rowptr[u + 1];
       const int64_t first = a + (int64_t)(p - inhub_base[lo]) * kHubPiece;
       const int64_t end = first + kHubPiece < c ? first + kHubPiece : c;
-      float part = 0.0f;
+      float4 part = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       for (int64_t k = first + threadIdx.x; k < end; k += kScatterBlock) {
-        const int32_t w = in_colidx[k];
-        if ((fb_row[w >> 5] >> (w & 31)) & 1u) part += inc_row[w];
+        const float4 v = grow[in_colidx[k]];
+        part.x += v.x;
+        part.y += v.y;
+        part.z += v.z;
+        part.w += v.w;
       }
-      const float sum = block_sum(part, s_tmpf);
-      if (threadIdx.x == 0 && sum > 0.0f) {
-        const size_t gi = (size_t)b * n + u;
-        const float old = unsafeAtomicAdd(&r[gi], sum);
-        const float now = old + sum;
-        const double thr = rmax * (double)info[u].y;
-        if ((double)old <= thr && (double)now > thr) nq.push(((u64)b << 32) | (uint32_t)u);
+      float sums[kPullGroup];
+      sums[0] = block_sum(part.x, s_tmpf);
+      sums[1] = block_sum(part.y, s_tmpf);
+      sums[2] = block_sum(part.z, s_tmpf);
+      sums[3] = block_sum(part.w, s_tmpf);
+      if (threadIdx.x == 0) {
+        const double d_u = (double)info[u].y;
+        for (int g = 0; g < kPullGroup; ++g) {
+          if (!((mask >> g) & 1u) || !(sums[g] > 0.0f)) continue;
+          const int b = grp * kPullGroup + g;
+          const size_t gi = (size_t)b * n + u;
+          const float old = unsafeAtomicAdd(&r[gi], sums[g]);
+          const float now = old + sums[g];
+          const double thr = Q[b].rmax * d_u;
+          if ((double)old <= thr && (double)now > thr) nq.push(((u64)b << 32) | (uint32_t)u);
+        }
       }
     }
     // flush when the LDS queue is half full (decision taken after a barrier,
@@ -341,7 +375,6 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
 __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
     int t, Ctrl* ctrl, const u64* __restrict__ fr_in, const float* __restrict__ frx,
     u64* __restrict__ fr_out, u64 cap, float* __restrict__ r, float* __restrict__ incd,
-    uint32_t* __restrict__ fbits,
     const int32_t* __restrict__ mode, const int32_t* __restrict__ stop,
     const QueryDev* __restrict__ Q, const int2* __restrict__ info,
     const int32_t* __restrict__ colidx, const int32_t* __restrict__ rank, int n,
@@ -368,17 +401,11 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
   }
   const NextQueue nq{s_queue, &s_qn, &s_qbase, &ctrl->fr_cnt[(t + 1) & 1], fr_out, cap, ctrl};
   if (threadIdx.x == 0) s_qn = 0;
-  // the dense increments and frontier bits were read by the pull launch;
-  // clear them (a bit word holds only this round's frontier, so whole words
-  // are zeroed)
-  const size_t nw = ((size_t)n + 31) >> 5;
+  // the dense increments were read by the pull launch; clear them
   for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
        i += (u64)gridDim.x * blockDim.x) {
     const u64 e = fr_in[i];
-    const size_t b = (size_t)(e >> 32);
-    const int32_t rk = rank[(uint32_t)e];
-    incd[b * n + rk] = 0.0f;
-    fbits[b * nw + (rk >> 5)] = 0u;
+    incd[incd_index((int)(e >> 32), rank[(uint32_t)e], n)] = 0.0f;
   }
   __syncthreads();
 
@@ -496,18 +523,18 @@ hipError_t launch_push_round(const GraphDev& g, const Ws& w, const Layout& L, in
   const size_t smem = (size_t)batch * (sizeof(u64) + sizeof(uint32_t));
   const u64 cap = (u64)L.cap;
   k_push_snapshot<<<blocks, 256, smem, s>>>(t, w.ctrl, w.fr[par], w.frx, w.r, w.q, w.incd,
-                                            w.fbits, w.queries, w.qstats, w.ecnt, g.info, g.rank, w.stop,
+                                            w.queries, w.qstats, w.ecnt, g.info, g.rank, w.stop,
                                             g.n, batch,
                                             frontier_log, log_cap, cap, w.hub_idx, w.hub_base,
                                             (u64)L.hub_cap);
   k_push_mode<<<1, 256, 0, s>>>(t, w.ctrl, w.ecnt, w.mode, w.pull_list, w.qstats, w.queries,
                                 w.stop, batch, (u64)g.n + (u64)g.m, pull_ratio);
   k_push_pull<<<blocks, kScatterBlock, 0, s>>>(t, w.ctrl, w.fr[par ^ 1], cap, w.r, w.incd,
-                                               w.fbits, w.queries, w.pull_list, g.info, g.in_rowptr,
+                                               w.queries, w.pull_list, g.info, g.in_rowptr,
                                                g.in_colidx, g.inhub_node, g.inhub_base,
                                                g.n_inhubs, g.inhub_pieces, g.n);
   k_push_scatter<<<blocks, kScatterBlock, 0, s>>>(t, w.ctrl, w.fr[par], w.frx, w.fr[par ^ 1],
-                                                  cap, w.r, w.incd, w.fbits, w.mode, w.stop,
+                                                  cap, w.r, w.incd, w.mode, w.stop,
                                                   w.queries,
                                                   g.info, g.colidx, g.rank, g.n, w.hub_idx,
                                                   w.hub_base,

@@ -159,6 +159,29 @@ def test_mixed_parameters_match_single_calls(g1k, G1k):
         assert bat.stats[b]["rounds"] == ref["rounds"]
 
 
+def test_many_pulling_queries_match_single_calls(g1k, G1k):
+    # 19 queries pull in the same rounds: groups of 8, 8 and 3 share each
+    # chunk's in-edge scan; every row must equal its query run alone
+    srcs = [int(x) for x in np.random.default_rng(5).integers(0, g1k.n, 19)]
+    seeds = list(range(19))
+    qs = fora.make_queries(srcs, k=50, seed=seeds, n=g1k.n, flags=WC)
+    B = len(srcs)
+    ws = fora.workspace(G1k, B)
+    bat = fora.fora_ssppr_batch(G1k, qs, ws=ws, stats=True)
+    got = _rows(G1k, B, ws)
+    assert sum(s["pull_rounds"] for s in bat.stats) >= 3 * B
+    ws1 = fora.workspace(G1k, 1)
+    for b in range(B):
+        single = fora.fora_ssppr(G1k, srcs[b], k=50, seed=seeds[b], ws=ws1, stats=True,
+                                 flags=WC)
+        one = _rows(G1k, 1, ws1)
+        _same_query(got, one, b, 0, single.stats["omega_unit"])
+        assert bat.stats[b]["rounds"] == single.stats["rounds"]
+        assert bat.stats[b]["pull_rounds"] == single.stats["pull_rounds"]
+    ref = oracle.fora(g1k, srcs[0], k=50, seed=seeds[0])
+    assert bat.stats[0]["rounds"] == ref["rounds"]
+
+
 def test_autotune_sets_and_caches(g1k, G1k, tmp_path):
     qs = fora.make_queries([0, 1, 2, 3], k=50, n=g1k.n)
     path = str(tmp_path / "tune.json")
