@@ -157,12 +157,12 @@ struct Ws {
   float* frx;
   u64* hub_idx;   // frontier index of each split entry
   u64* hub_base;  // first piece number of each split entry
-  float* incd;    // [ceil(batch / 4)][n][4]: frontier increments by degree rank, four
-                  // queries per node unit, dense, for pull rounds
+  float* incd;    // [ceil(batch / G)][n][G]: frontier increments by degree rank, G
+                  // queries per node unit (G <= 16), dense, for pull rounds
   u64* ecnt;      // [2][batch][kStatSlots]: frontier edges per query, by round parity
   int32_t* mode;  // [batch]: 1 if the query's current round pulls
-  int32_t* pull_list;  // groups of 4 queries with one in pull mode this round:
-                       // group << 4 | mask of the pulling members
+  int32_t* pull_list;  // groups of queries with one in pull mode this round:
+                       // group << 16 | mask of the pulling members
   int32_t* stop;       // [batch]: 0, or 1 + the first round the balance rule skips
   u64* plan_gi;
   u64* plan_off;

@@ -21,10 +21,10 @@
 //   The dense increments sit at each node's degree rank (GraphDev::rank),
 //   and the reverse graph stores in-neighbours by rank, so the gathers of
 //   high-degree nodes' increments (the most frequent ones) share lines.
-//   Queries are taken in groups of four, whose increments for one node form
-//   one 16-byte unit: a pull reads each in-edge's source once per group
-//   (one load), so the random reads per in-edge do not grow with the
-//   number of pulling queries.
+//   Queries are taken in groups of kPullGroup, whose increments for one
+//   node form one unit (32 bytes, one sector): a pull reads each in-edge's
+//   source once per group, so the random reads per in-edge do not grow
+//   with the number of pulling queries.
 //   Nodes of in-degree above kHubDeg are summed in pieces by any block and
 //   added with one atomic per piece.
 #include "internal.h"
@@ -33,11 +33,14 @@
 namespace fora {
 
 constexpr int kScatterBlock = 256;
-constexpr int kPullGroup = 4;  // queries per increment unit
+constexpr int kPullGroup = 16;             // queries per increment unit
+constexpr int kPullVec = kPullGroup / 4;   // float4 loads per unit
+static_assert(kPullGroup % 4 == 0 && kPullGroup <= 16 && 64 % kPullGroup == 0, "pull group");
 
 // Position of query b's increment for the node of degree rank rk.
 __device__ __forceinline__ size_t incd_index(int b, int32_t rk, int n) {
-  return ((size_t)(b >> 2) * (size_t)n + (size_t)rk) * kPullGroup + (size_t)(b & 3);
+  return ((size_t)(b / kPullGroup) * (size_t)n + (size_t)rk) * kPullGroup +
+         (size_t)(b % kPullGroup);
 }
 constexpr unsigned kQueueCap = 1024;  // LDS-staged next-frontier entries per block
 
@@ -145,8 +148,8 @@ __global__ __launch_bounds__(256) void k_push_snapshot(
 }
 
 // One block: choose pull or push for every query's round t; list the
-// groups of four queries with a pulling member; clear the next round's
-// frontier-edge slots.
+// groups of kPullGroup queries with a pulling member; clear the next
+// round's frontier-edge slots.
 __global__ __launch_bounds__(256) void k_push_mode(int t, Ctrl* ctrl, u64* ecnt, int32_t* mode,
                                                    int32_t* pull_list, StatSlot* slots,
                                                    const QueryDev* __restrict__ Q,
@@ -179,14 +182,16 @@ __global__ __launch_bounds__(256) void k_push_mode(int t, Ctrl* ctrl, u64* ecnt,
         }
       }
     }
-    // lanes 4k..4k+3 of a wave hold one group (base is a multiple of 256)
+    // aligned runs of kPullGroup lanes hold one group (base is a multiple
+    // of 256)
     const unsigned lane = threadIdx.x & 63;
     const u64 bal = __ballot(pull != 0);
-    const int32_t gmask = (int32_t)((bal >> (lane & ~3u)) & 0xFull);
-    const int32_t lead = ((lane & 3u) == 0 && gmask != 0) ? 1 : 0;
+    const int32_t gmask =
+        (int32_t)((bal >> (lane & ~(unsigned)(kPullGroup - 1))) & ((1ull << kPullGroup) - 1));
+    const int32_t lead = ((lane & (unsigned)(kPullGroup - 1)) == 0 && gmask != 0) ? 1 : 0;
     int32_t tot;
     const int32_t pos = carry + block_exclusive_scan(lead, s_tmp, tot);
-    if (lead) pull_list[pos] = ((b >> 2) << 4) | gmask;
+    if (lead) pull_list[pos] = ((b / kPullGroup) << 16) | gmask;
     carry += tot;
   }
   for (size_t i = threadIdx.x; i < (size_t)batch * kStatSlots; i += 256) ec_next[i] = 0;
@@ -247,8 +252,8 @@ __device__ __forceinline__ void push_edge(int b, int u, float inc, double rmax,
 // Items: (chunk of kScatterBlock destination nodes, pull group), then
 // (piece of a high-in-degree node, pull group). A chunk item scans the
 // chunk's in-degrees, finds each in-edge's owner, and reads the source's
-// four increments with one 16-byte load; each pulling member of the group
-// sums its own increment into its LDS row.
+// increment unit once; each pulling member of the group sums its own
+// increment into its LDS row.
 __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
     int t, Ctrl* ctrl, u64* __restrict__ fr_out, u64 cap, float* __restrict__ r,
     const float* __restrict__ incd, const QueryDev* __restrict__ Q,
@@ -278,9 +283,9 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
     const bool is_chunk = it < chunk_items;
     const u64 gidx = is_chunk ? it / chunks : (it - chunk_items) / inhub_pieces;
     const int32_t entry = pull_list[gidx];
-    const int grp = entry >> 4;
-    const unsigned mask = (unsigned)entry & 15u;
-    const float4* grow = inc4 + (size_t)grp * n;
+    const int grp = entry >> 16;
+    const unsigned mask = (unsigned)entry & 0xFFFFu;
+    const float4* grow = inc4 + (size_t)grp * n * kPullVec;
     if (is_chunk) {
       const u64 j = it % chunks;
       const int u0 = (int)(j * kScatterBlock);
@@ -304,11 +309,17 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
           if (s_pre[mid] <= k) lo = mid;
           else hi = mid - 1;
         }
-        const float4 v = grow[in_colidx[(int64_t)s_start[lo] + (int64_t)(k - s_pre[lo])]];
-        if ((mask & 1u) && v.x != 0.0f) atomicAdd(&s_sum[0][lo], v.x);
-        if ((mask & 2u) && v.y != 0.0f) atomicAdd(&s_sum[1][lo], v.y);
-        if ((mask & 4u) && v.z != 0.0f) atomicAdd(&s_sum[2][lo], v.z);
-        if ((mask & 8u) && v.w != 0.0f) atomicAdd(&s_sum[3][lo], v.w);
+        const float4* unit =
+            grow + (size_t)in_colidx[(int64_t)s_start[lo] + (int64_t)(k - s_pre[lo])] * kPullVec;
+#pragma unroll
+        for (int h = 0; h < kPullVec; ++h) {
+          const float4 v = unit[h];
+          const unsigned m = mask >> (4 * h);
+          if ((m & 1u) && v.x != 0.0f) atomicAdd(&s_sum[4 * h][lo], v.x);
+          if ((m & 2u) && v.y != 0.0f) atomicAdd(&s_sum[4 * h + 1][lo], v.y);
+          if ((m & 4u) && v.z != 0.0f) atomicAdd(&s_sum[4 * h + 2][lo], v.z);
+          if ((m & 8u) && v.w != 0.0f) atomicAdd(&s_sum[4 * h + 3][lo], v.w);
+        }
       }
       __syncthreads();
       if (u < n) {
@@ -337,19 +348,22 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
       const int64_t a = in_rowptr[u], c = in_rowptr[u + 1];
       const int64_t first = a + (int64_t)(p - inhub_base[lo]) * kHubPiece;
       const int64_t end = first + kHubPiece < c ? first + kHubPiece : c;
-      float4 part = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      float part[kPullGroup];
+      for (int g = 0; g < kPullGroup; ++g) part[g] = 0.0f;
       for (int64_t k = first + threadIdx.x; k < end; k += kScatterBlock) {
-        const float4 v = grow[in_colidx[k]];
-        part.x += v.x;
-        part.y += v.y;
-        part.z += v.z;
-        part.w += v.w;
+        const float4* unit = grow + (size_t)in_colidx[k] * kPullVec;
+#pragma unroll
+        for (int h = 0; h < kPullVec; ++h) {
+          const float4 v = unit[h];
+          part[4 * h] += v.x;
+          part[4 * h + 1] += v.y;
+          part[4 * h + 2] += v.z;
+          part[4 * h + 3] += v.w;
+        }
       }
       float sums[kPullGroup];
-      sums[0] = block_sum(part.x, s_tmpf);
-      sums[1] = block_sum(part.y, s_tmpf);
-      sums[2] = block_sum(part.z, s_tmpf);
-      sums[3] = block_sum(part.w, s_tmpf);
+      for (int g = 0; g < kPullGroup; ++g)
+        sums[g] = ((mask >> g) & 1u) ? block_sum(part[g], s_tmpf) : 0.0f;
       if (threadIdx.x == 0) {
         const double d_u = (double)info[u].y;
         for (int g = 0; g < kPullGroup; ++g) {
