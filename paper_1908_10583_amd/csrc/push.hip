@@ -302,24 +302,49 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
       s_pre[threadIdx.x] = pre;
       __syncthreads();
       const int last = (n - u0 < kScatterBlock ? n - u0 : kScatterBlock) - 1;
-      for (u64 k = threadIdx.x; k < total; k += kScatterBlock) {
+      // merge path: thread t takes the in-edges [t per, (t + 1) per) of the
+      // chunk in order, sums each node's run in registers and adds the sums
+      // to LDS where a node's run ends
+      const u64 per = (total + kScatterBlock - 1) / kScatterBlock;
+      u64 k = (u64)threadIdx.x * per;
+      const u64 kend = k + per < total ? k + per : total;
+      if (k < kend) {
+        // owner of k: the largest index with s_pre <= k (it has in-edges)
         int lo = 0, hi = last;
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
           if (s_pre[mid] <= k) lo = mid;
           else hi = mid - 1;
         }
-        const float4* unit =
-            grow + (size_t)in_colidx[(int64_t)s_start[lo] + (int64_t)(k - s_pre[lo])] * kPullVec;
+        u64 run_end = lo < last ? s_pre[lo + 1] : total;
+        float acc[kPullGroup];
 #pragma unroll
-        for (int h = 0; h < kPullVec; ++h) {
-          const float4 v = unit[h];
-          const unsigned m = mask >> (4 * h);
-          if ((m & 1u) && v.x != 0.0f) atomicAdd(&s_sum[4 * h][lo], v.x);
-          if ((m & 2u) && v.y != 0.0f) atomicAdd(&s_sum[4 * h + 1][lo], v.y);
-          if ((m & 4u) && v.z != 0.0f) atomicAdd(&s_sum[4 * h + 2][lo], v.z);
-          if ((m & 8u) && v.w != 0.0f) atomicAdd(&s_sum[4 * h + 3][lo], v.w);
+        for (int g = 0; g < kPullGroup; ++g) acc[g] = 0.0f;
+        auto flush = [&](int node) {
+#pragma unroll
+          for (int g = 0; g < kPullGroup; ++g) {
+            if (((mask >> g) & 1u) && acc[g] != 0.0f) atomicAdd(&s_sum[g][node], acc[g]);
+            acc[g] = 0.0f;
+          }
+        };
+        for (; k < kend; ++k) {
+          while (k >= run_end) {  // the node's run ended: move to the next with in-edges
+            flush(lo);
+            ++lo;
+            run_end = lo < last ? s_pre[lo + 1] : total;
+          }
+          const float4* unit =
+              grow + (size_t)in_colidx[(int64_t)s_start[lo] + (int64_t)(k - s_pre[lo])] * kPullVec;
+#pragma unroll
+          for (int h = 0; h < kPullVec; ++h) {
+            const float4 v = unit[h];
+            acc[4 * h] += v.x;
+            acc[4 * h + 1] += v.y;
+            acc[4 * h + 2] += v.z;
+            acc[4 * h + 3] += v.w;
+          }
         }
+        flush(lo);
       }
       __syncthreads();
       if (u < n) {
