@@ -452,7 +452,8 @@ Layout make_layout(const GraphDev& g, int32_t batch) {
   L.acc = take(8 * cap);
   L.hist = take(4 * (size_t)kHistBins * batch);
   L.cand_cnt = take(4 * (size_t)batch);
-  L.incd = take(4 * (((size_t)batch + 15) / 16 * 16) * (size_t)n);  // whole pull groups
+  const size_t pg = (size_t)pull_group_for(batch);
+  L.incd = take(4 * (((size_t)batch + pg - 1) / pg * pg) * (size_t)n);  // whole pull groups
   L.ecnt = take(8 * 2 * (size_t)kStatSlots * batch);
   L.stop = take(4 * (size_t)batch);
   L.zero_end = align_up(off, 256);

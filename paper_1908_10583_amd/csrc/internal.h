@@ -131,6 +131,13 @@ struct GraphDev {
   const int32_t* idx_dest;
 };
 
+// Queries per unit of the dense pull increments (1, 4 or 16): one pull
+// load serves that many queries; small batches take small units so that a
+// single query does not read and clear sixteen queries' worth.
+__host__ __device__ inline int pull_group_for(int batch) {
+  return batch >= 16 ? 16 : (batch >= 4 ? 4 : 1);
+}
+
 struct Layout {
   size_t ctrl, qstats, queries, r, q, cnt, acc, pi;
   size_t fr0, fr1, frx, hub_idx, hub_base, incd, ecnt, mode, pull_list, stop;
@@ -157,8 +164,8 @@ struct Ws {
   float* frx;
   u64* hub_idx;   // frontier index of each split entry
   u64* hub_base;  // first piece number of each split entry
-  float* incd;    // [ceil(batch / G)][n][G]: frontier increments by degree rank, G
-                  // queries per node unit (G <= 16), dense, for pull rounds
+  float* incd;    // [ceil(batch / G)][n][G]: frontier increments by degree rank, G =
+                  // pull_group_for(batch) queries per node unit, dense, for pull rounds
   u64* ecnt;      // [2][batch][kStatSlots]: frontier edges per query, by round parity
   int32_t* mode;  // [batch]: 1 if the query's current round pulls
   int32_t* pull_list;  // groups of queries with one in pull mode this round:

@@ -21,10 +21,11 @@
 //   The dense increments sit at each node's degree rank (GraphDev::rank),
 //   and the reverse graph stores in-neighbours by rank, so the gathers of
 //   high-degree nodes' increments (the most frequent ones) share lines.
-//   Queries are taken in groups of kPullGroup, whose increments for one
-//   node form one unit (32 bytes, one sector): a pull reads each in-edge's
-//   source once per group, so the random reads per in-edge do not grow
-//   with the number of pulling queries.
+//   Queries are taken in groups of G = pull_group_for(batch) (16 for
+//   large batches), whose increments for one node form one unit (64 bytes
+//   at G = 16): a pull reads each in-edge's source once per group, so the
+//   random reads per in-edge do not grow with the number of pulling
+//   queries.
 //   Nodes of in-degree above kHubDeg are summed in pieces by any block and
 //   added with one atomic per piece.
 #include "internal.h"
@@ -33,14 +34,30 @@
 namespace fora {
 
 constexpr int kScatterBlock = 256;
-constexpr int kPullGroup = 16;             // queries per increment unit
-constexpr int kPullVec = kPullGroup / 4;   // float4 loads per unit
-static_assert(kPullGroup % 4 == 0 && kPullGroup <= 16 && 64 % kPullGroup == 0, "pull group");
+// Position of query b's increment for the node of degree rank rk, with G
+// queries per unit (a power of two).
+__device__ __forceinline__ size_t incd_index(int b, int32_t rk, int n, int G) {
+  return ((size_t)(b / G) * (size_t)n + (size_t)rk) * (size_t)G + (size_t)(b % G);
+}
 
-// Position of query b's increment for the node of degree rank rk.
-__device__ __forceinline__ size_t incd_index(int b, int32_t rk, int n) {
-  return ((size_t)(b / kPullGroup) * (size_t)n + (size_t)rk) * kPullGroup +
-         (size_t)(b % kPullGroup);
+// The G increments of unit w of a group's rows.
+template <int G>
+__device__ __forceinline__ void load_unit(const float* __restrict__ grow, int32_t w,
+                                          float (&v)[G]) {
+  if constexpr (G == 1) {
+    v[0] = grow[w];
+  } else {
+    static_assert(G % 4 == 0, "units of four");
+    const float4* u = reinterpret_cast<const float4*>(grow) + (size_t)w * (G / 4);
+#pragma unroll
+    for (int h = 0; h < G / 4; ++h) {
+      const float4 x = u[h];
+      v[4 * h] = x.x;
+      v[4 * h + 1] = x.y;
+      v[4 * h + 2] = x.z;
+      v[4 * h + 3] = x.w;
+    }
+  }
 }
 constexpr unsigned kQueueCap = 1024;  // LDS-staged next-frontier entries per block
 
@@ -113,7 +130,7 @@ __global__ __launch_bounds__(256) void k_push_snapshot(
     const int d = info[v].y;
     const float inc = (float)(((1.0 - alpha) * (double)x) / (double)d);
     frx[i] = inc;
-    incd[incd_index(b, rank[v], n)] = inc;
+    incd[incd_index(b, rank[v], n, pull_group_for(batch))] = inc;
     if (d > kHubDeg) {
       const u64 pieces = (u64)((d + kHubPiece - 1) / kHubPiece);
       const u64 old = atomicAdd(&ctrl->hub_ctr[t & 1], (1ull << 40) | pieces);
@@ -148,8 +165,8 @@ __global__ __launch_bounds__(256) void k_push_snapshot(
 }
 
 // One block: choose pull or push for every query's round t; list the
-// groups of kPullGroup queries with a pulling member; clear the next
-// round's frontier-edge slots.
+// groups of pull_group_for(batch) queries with a pulling member; clear the
+// next round's frontier-edge slots.
 __global__ __launch_bounds__(256) void k_push_mode(int t, Ctrl* ctrl, u64* ecnt, int32_t* mode,
                                                    int32_t* pull_list, StatSlot* slots,
                                                    const QueryDev* __restrict__ Q,
@@ -182,16 +199,15 @@ __global__ __launch_bounds__(256) void k_push_mode(int t, Ctrl* ctrl, u64* ecnt,
         }
       }
     }
-    // aligned runs of kPullGroup lanes hold one group (base is a multiple
-    // of 256)
+    // aligned runs of G lanes hold one group (base is a multiple of 256)
+    const unsigned G = (unsigned)pull_group_for(batch);
     const unsigned lane = threadIdx.x & 63;
     const u64 bal = __ballot(pull != 0);
-    const int32_t gmask =
-        (int32_t)((bal >> (lane & ~(unsigned)(kPullGroup - 1))) & ((1ull << kPullGroup) - 1));
-    const int32_t lead = ((lane & (unsigned)(kPullGroup - 1)) == 0 && gmask != 0) ? 1 : 0;
+    const int32_t gmask = (int32_t)((bal >> (lane & ~(G - 1))) & ((1ull << G) - 1));
+    const int32_t lead = ((lane & (G - 1)) == 0 && gmask != 0) ? 1 : 0;
     int32_t tot;
     const int32_t pos = carry + block_exclusive_scan(lead, s_tmp, tot);
-    if (lead) pull_list[pos] = ((b / kPullGroup) << 16) | gmask;
+    if (lead) pull_list[pos] = ((b / (int)G) << 16) | gmask;
     carry += tot;
   }
   for (size_t i = threadIdx.x; i < (size_t)batch * kStatSlots; i += 256) ec_next[i] = 0;
@@ -254,6 +270,7 @@ __device__ __forceinline__ void push_edge(int b, int u, float inc, double rmax,
 // chunk's in-degrees, finds each in-edge's owner, and reads the source's
 // increment unit once; each pulling member of the group sums its own
 // increment into its LDS row.
+template <int G>
 __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
     int t, Ctrl* ctrl, u64* __restrict__ fr_out, u64 cap, float* __restrict__ r,
     const float* __restrict__ incd, const QueryDev* __restrict__ Q,
@@ -263,7 +280,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
     u64 inhub_pieces, int n) {
   __shared__ u64 s_pre[kScatterBlock];
   __shared__ int32_t s_start[kScatterBlock];
-  __shared__ float s_sum[kPullGroup][kScatterBlock];
+  __shared__ float s_sum[G][kScatterBlock];
   __shared__ u64 s_queue[kQueueCap];
   __shared__ unsigned s_qn;
   __shared__ u64 s_qbase;
@@ -275,7 +292,6 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
   const NextQueue nq{s_queue, &s_qn, &s_qbase, &ctrl->fr_cnt[(t + 1) & 1], fr_out, cap, ctrl};
   if (threadIdx.x == 0) s_qn = 0;
   __syncthreads();
-  const float4* inc4 = reinterpret_cast<const float4*>(incd);
   const u64 chunks = ((u64)n + kScatterBlock - 1) / kScatterBlock;
   const u64 chunk_items = chunks * (u64)ngroups;
   const u64 items = chunk_items + inhub_pieces * (u64)ngroups;
@@ -285,7 +301,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
     const int32_t entry = pull_list[gidx];
     const int grp = entry >> 16;
     const unsigned mask = (unsigned)entry & 0xFFFFu;
-    const float4* grow = inc4 + (size_t)grp * n * kPullVec;
+    const float* grow = incd + (size_t)grp * n * G;
     if (is_chunk) {
       const u64 j = it % chunks;
       const int u0 = (int)(j * kScatterBlock);
@@ -296,7 +312,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
         s_start[threadIdx.x] = a;
         deg = (c - a) > kHubDeg ? 0ull : (u64)(c - a);
       }
-      for (int g = 0; g < kPullGroup; ++g) s_sum[g][threadIdx.x] = 0.0f;
+      for (int g = 0; g < G; ++g) s_sum[g][threadIdx.x] = 0.0f;
       u64 total;
       const u64 pre = block_exclusive_scan(deg, s_tmp, total);
       s_pre[threadIdx.x] = pre;
@@ -317,12 +333,12 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
           else hi = mid - 1;
         }
         u64 run_end = lo < last ? s_pre[lo + 1] : total;
-        float acc[kPullGroup];
+        float acc[G];
 #pragma unroll
-        for (int g = 0; g < kPullGroup; ++g) acc[g] = 0.0f;
+        for (int g = 0; g < G; ++g) acc[g] = 0.0f;
         auto flush = [&](int node) {
 #pragma unroll
-          for (int g = 0; g < kPullGroup; ++g) {
+          for (int g = 0; g < G; ++g) {
             if (((mask >> g) & 1u) && acc[g] != 0.0f) atomicAdd(&s_sum[g][node], acc[g]);
             acc[g] = 0.0f;
           }
@@ -333,26 +349,20 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
             ++lo;
             run_end = lo < last ? s_pre[lo + 1] : total;
           }
-          const float4* unit =
-              grow + (size_t)in_colidx[(int64_t)s_start[lo] + (int64_t)(k - s_pre[lo])] * kPullVec;
+          float v[G];
+          load_unit<G>(grow, in_colidx[(int64_t)s_start[lo] + (int64_t)(k - s_pre[lo])], v);
 #pragma unroll
-          for (int h = 0; h < kPullVec; ++h) {
-            const float4 v = unit[h];
-            acc[4 * h] += v.x;
-            acc[4 * h + 1] += v.y;
-            acc[4 * h + 2] += v.z;
-            acc[4 * h + 3] += v.w;
-          }
+          for (int g = 0; g < G; ++g) acc[g] += v[g];
         }
         flush(lo);
       }
       __syncthreads();
       if (u < n) {
         const double d_u = (double)info[u].y;
-        for (int g = 0; g < kPullGroup; ++g) {
+        for (int g = 0; g < G; ++g) {
           const float add = s_sum[g][threadIdx.x];
           if (((mask >> g) & 1u) && add > 0.0f) {
-            const int b = grp * kPullGroup + g;
+            const int b = grp * G + g;
             const size_t gi = (size_t)b * n + u;
             const float now = r[gi] + add;
             r[gi] = now;
@@ -373,27 +383,23 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
       const int64_t a = in_rowptr[u], c = in_rowptr[u + 1];
       const int64_t first = a + (int64_t)(p - inhub_base[lo]) * kHubPiece;
       const int64_t end = first + kHubPiece < c ? first + kHubPiece : c;
-      float part[kPullGroup];
-      for (int g = 0; g < kPullGroup; ++g) part[g] = 0.0f;
-      for (int64_t k = first + threadIdx.x; k < end; k += kScatterBlock) {
-        const float4* unit = grow + (size_t)in_colidx[k] * kPullVec;
+      float part[G];
 #pragma unroll
-        for (int h = 0; h < kPullVec; ++h) {
-          const float4 v = unit[h];
-          part[4 * h] += v.x;
-          part[4 * h + 1] += v.y;
-          part[4 * h + 2] += v.z;
-          part[4 * h + 3] += v.w;
-        }
+      for (int g = 0; g < G; ++g) part[g] = 0.0f;
+      for (int64_t k = first + threadIdx.x; k < end; k += kScatterBlock) {
+        float v[G];
+        load_unit<G>(grow, in_colidx[k], v);
+#pragma unroll
+        for (int g = 0; g < G; ++g) part[g] += v[g];
       }
-      float sums[kPullGroup];
-      for (int g = 0; g < kPullGroup; ++g)
+      float sums[G];
+      for (int g = 0; g < G; ++g)
         sums[g] = ((mask >> g) & 1u) ? block_sum(part[g], s_tmpf) : 0.0f;
       if (threadIdx.x == 0) {
         const double d_u = (double)info[u].y;
-        for (int g = 0; g < kPullGroup; ++g) {
+        for (int g = 0; g < G; ++g) {
           if (!((mask >> g) & 1u) || !(sums[g] > 0.0f)) continue;
-          const int b = grp * kPullGroup + g;
+          const int b = grp * G + g;
           const size_t gi = (size_t)b * n + u;
           const float old = unsafeAtomicAdd(&r[gi], sums[g]);
           const float now = old + sums[g];
@@ -417,7 +423,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
     const int32_t* __restrict__ mode, const int32_t* __restrict__ stop,
     const QueryDev* __restrict__ Q, const int2* __restrict__ info,
     const int32_t* __restrict__ colidx, const int32_t* __restrict__ rank, int n,
-    const u64* __restrict__ hub_idx,
+    int pull_group, const u64* __restrict__ hub_idx,
     const u64* __restrict__ hub_base, u64 hub_cap) {
   __shared__ u64 s_pre[kScatterBlock];
   __shared__ int32_t s_start[kScatterBlock];
@@ -444,7 +450,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
   for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
        i += (u64)gridDim.x * blockDim.x) {
     const u64 e = fr_in[i];
-    incd[incd_index((int)(e >> 32), rank[(uint32_t)e], n)] = 0.0f;
+    incd[incd_index((int)(e >> 32), rank[(uint32_t)e], n, pull_group)] = 0.0f;
   }
   __syncthreads();
 
@@ -568,16 +574,16 @@ hipError_t launch_push_round(const GraphDev& g, const Ws& w, const Layout& L, in
                                             (u64)L.hub_cap);
   k_push_mode<<<1, 256, 0, s>>>(t, w.ctrl, w.ecnt, w.mode, w.pull_list, w.qstats, w.queries,
                                 w.stop, batch, (u64)g.n + (u64)g.m, pull_ratio);
-  k_push_pull<<<blocks, kScatterBlock, 0, s>>>(t, w.ctrl, w.fr[par ^ 1], cap, w.r, w.incd,
-                                               w.queries, w.pull_list, g.info, g.in_rowptr,
-                                               g.in_colidx, g.inhub_node, g.inhub_base,
-                                               g.n_inhubs, g.inhub_pieces, g.n);
+  const int pg = pull_group_for(batch);
+  auto pull = pg == 16 ? k_push_pull<16> : (pg == 4 ? k_push_pull<4> : k_push_pull<1>);
+  pull<<<blocks, kScatterBlock, 0, s>>>(t, w.ctrl, w.fr[par ^ 1], cap, w.r, w.incd, w.queries,
+                                        w.pull_list, g.info, g.in_rowptr, g.in_colidx,
+                                        g.inhub_node, g.inhub_base, g.n_inhubs, g.inhub_pieces,
+                                        g.n);
   k_push_scatter<<<blocks, kScatterBlock, 0, s>>>(t, w.ctrl, w.fr[par], w.frx, w.fr[par ^ 1],
-                                                  cap, w.r, w.incd, w.mode, w.stop,
-                                                  w.queries,
-                                                  g.info, g.colidx, g.rank, g.n, w.hub_idx,
-                                                  w.hub_base,
-                                                  (u64)L.hub_cap);
+                                                  cap, w.r, w.incd, w.mode, w.stop, w.queries,
+                                                  g.info, g.colidx, g.rank, g.n, pg, w.hub_idx,
+                                                  w.hub_base, (u64)L.hub_cap);
   return hipGetLastError();
 }
 
