@@ -24,8 +24,10 @@ import torch
 
 from . import fora
 
-MULTS = np.exp(np.linspace(math.log(8.0), math.log(0.25), 12))  # descending
-LOG_LO, LOG_HI = math.log(0.25), math.log(8.0)
+MULTS = np.exp(np.linspace(math.log(8.0), math.log(1.0 / 32), 16))  # descending
+LOG_LO, LOG_HI = math.log(1.0 / 32), math.log(8.0)
+# the output range of models saved before the grid reached below 0.25 r_max*
+LEGACY_LOG_RANGE = (math.log(0.25), math.log(8.0))
 
 
 def features(G, srcs, alpha=0.2, eps=0.5, delta=None, pf=None):
@@ -53,26 +55,39 @@ def sweep(G, srcs, alpha=0.2, eps=0.5, delta=None, pf=None, batch=128, log=None)
     return E, W
 
 
-def calibrate(G, srcs, alpha=0.2, eps=0.5, mults=(0.25, 1.0, 8.0), batch=64):
-    """Per-unit costs measured on this GPU: ms per residue increment (push)
-    and ms per walk, from batched FORA calls at several r_max multipliers."""
+def calibrate(G, srcs, alpha=0.2, eps=0.5, mults=(1 / 32, 1 / 8, 0.5, 1.0, 2.0, 8.0),
+              batch=64):
+    """Marginal per-unit costs on this GPU: ms per residue increment (push)
+    and ms per walk, the slopes of affine least-squares fits of each phase's
+    time against its work over batched FORA calls at several r_max
+    multipliers (the intercepts take the per-call and per-round overheads,
+    which do not scale with the work)."""
     srcs = np.asarray(srcs)[:batch]
     ws = fora.workspace(G, len(srcs))
-    push_ms = walk_ms = 0.0
-    E = W = 0
     fora.fora_ssppr_batch(G, fora.make_queries(srcs, alpha=alpha, eps=eps, k=1, n=G.n), ws=ws)
     c = fora.fora_ssppr_batch(G, fora.make_queries(srcs[:1], alpha=alpha, eps=eps, k=1, n=G.n),
                               ws=ws, stats=True).stats[0]
     rstar = c["rmax"]
+    rows = []
     for mlt in mults:
         qs = fora.make_queries(srcs, alpha=alpha, eps=eps, k=1, n=G.n, rmax=rstar * mlt)
-        st = fora.fora_ssppr_batch(G, qs, ws=ws, stats=True).stats
-        push_ms += st[0]["ms_push"]
-        walk_ms += st[0]["ms_walk"]
-        E += sum(s["edge_ops"] for s in st)
-        W += sum(s["walks"] for s in st)
-    return dict(ms_per_edge_op=push_ms / max(E, 1), ms_per_walk=walk_ms / max(W, 1),
-                rmax_star=rstar)
+        for _ in range(2):  # the second call is the one kept (warm)
+            st = fora.fora_ssppr_batch(G, qs, ws=ws, stats=True).stats
+        rows.append((st[0]["ms_push"], st[0]["ms_walk"], sum(s["edge_ops"] for s in st),
+                     sum(s["walks"] for s in st)))
+    r = np.asarray(rows, np.float64)
+
+    def slope(t, x):
+        A = np.stack([x, np.ones_like(x)], 1)
+        return float(np.linalg.lstsq(A, t, rcond=None)[0][0])
+
+    a = slope(r[:, 0], r[:, 2])
+    b = slope(r[:, 1], r[:, 3])
+    # a fit with a non-positive slope (noise) falls back to the average cost
+    a = a if a > 0 else float(r[:, 0].sum() / max(r[:, 2].sum(), 1.0))
+    b = b if b > 0 else float(r[:, 1].sum() / max(r[:, 3].sum(), 1.0))
+    return dict(ms_per_edge_op=a, ms_per_walk=b, rmax_star=rstar,
+                calibration=dict(mults=list(map(float, mults)), rows=r.tolist()))
 
 
 def labels(E, W, cost):
@@ -101,10 +116,14 @@ def labels(E, W, cost):
 class Model:
     """MLP parameters on the device (FP32 master copy, BF16 inference copy)."""
 
-    def __init__(self, params: torch.Tensor, trained_on=((0.2, 0.5),)):
+    def __init__(self, params: torch.Tensor, trained_on=((0.2, 0.5),),
+                 log_range=(LOG_LO, LOG_HI)):
         self.params = params
         # the (alpha, eps) pairs of the training set; other queries keep eqn:rmax
         self.trained_on = [tuple(map(float, x)) for x in trained_on]
+        # the label grid's range in ln(r_max / r_max*): predictions outside
+        # it fall back to eqn:rmax
+        self.log_range = tuple(map(float, log_range))
 
     def covers(self, alpha: float, eps: float) -> bool:
         return any(abs(alpha - a) < 1e-12 and abs(eps - e) < 1e-12 for a, e in self.trained_on)
@@ -178,19 +197,20 @@ class Model:
         if not torch.is_tensor(srcs):
             srcs = torch.as_tensor(np.asarray(srcs), dtype=torch.int32)
         return fora.fora_predict_rmax(G, srcs, self.bf16(), alpha, eps, delta, pf,
-                                      LOG_LO, LOG_HI)
+                                      *self.log_range)
 
     def save(self, path):
         with open(path, "w") as f:
             json.dump(dict(params=self.params.cpu().numpy().tolist(),
-                           trained_on=self.trained_on), f)
+                           trained_on=self.trained_on, log_range=self.log_range), f)
 
     @classmethod
     def load(cls, path, device="cuda"):
         with open(path) as f:
             d = json.load(f)
         p = np.asarray(d["params"], np.float32)
-        return cls(torch.from_numpy(p).to(device), d.get("trained_on", ((0.2, 0.5),)))
+        return cls(torch.from_numpy(p).to(device), d.get("trained_on", ((0.2, 0.5),)),
+                   d.get("log_range", LEGACY_LOG_RANGE))
 
 
 def time_queries(G, srcs, rmax=None, alpha=0.2, eps=0.5, k=500):

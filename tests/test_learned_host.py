@@ -24,3 +24,19 @@ def test_labels_find_the_minimum_of_a_balanced_cost():
     assert np.all((y >= x[-1] - 1e-12) & (y <= x[0] + 1e-12))
     assert np.all(y[~inside] == np.where(want[~inside] > x[0], x[0], x[-1]))
     assert total.shape == E.shape
+
+
+def test_model_file_keeps_its_output_range(tmp_path):
+    import json
+    import torch
+    from paper_1908_10583_amd import fora
+    path = str(tmp_path / "m.json")
+    m = learned.Model(torch.zeros(fora.FORA_MLP_PARAMS), log_range=(-1.0, 2.0))
+    m.save(path)
+    assert learned.Model.load(path, device="cpu").log_range == (-1.0, 2.0)
+    # a file without the field holds a model of the earlier grid, [0.25, 8] r_max*
+    d = json.load(open(path))
+    del d["log_range"]
+    json.dump(d, open(path, "w"))
+    assert learned.Model.load(path, device="cpu").log_range == learned.LEGACY_LOG_RANGE
+    assert abs(learned.MULTS[0] - 8.0) < 1e-12 and abs(learned.MULTS[-1] - 1 / 32) < 1e-15
