@@ -113,7 +113,10 @@ def main():
     waves = [(a, min(a + WB, B)) for a in range(0, B, WB)]
     qs_w = [fora.make_queries(srcs[a:b], alpha=alpha, eps=eps, k=k, seed=seed, n=g.n)
             for a, b in waves]
-    ws = fora.workspace(G, WB)
+    ws_bytes = fora.fora_workspace_size(G, WB)
+    if not args.no_topk:  # the top-k leg reuses it (staging rows after the main layout)
+        ws_bytes = max(ws_bytes, fora.fora_topk_workspace_size(G, WB, k))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda:0")
     ids = torch.empty((B, k), dtype=torch.int32, device="cuda:0")
     vals = torch.empty((B, k), dtype=torch.float32, device="cuda:0")
     log(f"workspace {ws.numel()/2**30:.2f} GiB for waves of {WB} ({len(waves)} waves)")
@@ -287,8 +290,7 @@ def main():
         # top-k FORA (Algorithm 5): the same sources and k, eps and p_f of the
         # workload, delta halving from 1/k until the k-th estimate clears it
         qk = fora.make_queries(srcs[:WB], alpha=alpha, eps=eps, k=k, seed=seed, n=g.n)
-        wsk = torch.empty(fora.fora_topk_workspace_size(G, len(qk), k), dtype=torch.uint8,
-                          device="cuda:0")
+        wsk = ws  # sized for both at the start (one workspace of this size fits in HBM)
         outk = (ids[:len(qk)], vals[:len(qk)])
         for _ in range(args.warmup):
             fora.fora_topk_batch(G, qk, kmax=k, ws=wsk, out=outk)
@@ -305,7 +307,6 @@ def main():
                         walks=sum(x["walks"] for x in rk.stats),
                         note="approximate top-k (Definition 2) by Algorithm 5, not the "
                              "whole-graph query; sources of the first wave")
-        del wsk
         log(f"top-k FORA (Algorithm 5): {topk_leg['queries_per_s']} q/s, "
             f"{topk_leg['iterations_mean']:.1f} iterations")
 

@@ -183,7 +183,9 @@ int fora_workspace_views(const fora_graph *g, int32_t batch, void *d_ws,
  *  top-k: ids sorted by (pi_hat descending, id ascending).
  * Output d_topk_ids int32[k], d_topk_vals float[k] (FP32 pi_hat). If fewer
  * than k nodes have pi_hat > 0 the rest are the lowest unused ids, value 0.
- * h_stats (nullable) makes the call wait and fill the counters.
+ * h_stats (nullable) makes the call wait and fill the counters. The query
+ * flags are 0 here (no per-node walk counts); fora_ssppr_batch with a batch
+ * of one takes flags.
  * Errors: FORA_E_ARG for any parameter outside the ranges of fora_query,
  * FORA_E_NOMEM if ws_bytes < fora_workspace_size(g, 1),
  * FORA_E_OVERFLOW if some omega_v >= 2^32 (the walk index j within a node
@@ -198,7 +200,7 @@ int fora_ssppr(const fora_graph *g, int32_t src, double alpha, double eps,
  * rounds, walk plans, walks and selections run in shared kernels. Query b's
  * result is written to d_ids[b*kmax ...], d_vals[b*kmax ...]; kmax must be at
  * least every query's k. Each query's result equals what fora_ssppr returns
- * for it (walk counts bit-identical given identical residues). h_stats
+ * for it (walk end points bit-identical given identical residues). h_stats
  * (nullable) is an array of `batch` entries.
  * With tuning.graph_rounds = R > 0 the whole sequence (zero fill, init, R
  * push rounds, plan, walks, top-k) is captured once per (batch, kmax,
