@@ -86,6 +86,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
     ap.add_argument("--no-alg3", action="store_true", help="skip the Algorithm 3 leg")
     ap.add_argument("--no-topk", action="store_true", help="skip the top-k FORA leg")
+    ap.add_argument("--no-pagerank", action="store_true", help="skip the global PageRank leg")
     ap.add_argument("--no-index", action="store_true", help="skip the FORA+ (index) leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy, whose HBM counter "
@@ -310,6 +311,26 @@ def main():
         log(f"top-k FORA (Algorithm 5): {topk_leg['queries_per_s']} q/s, "
             f"{topk_leg['iterations_mean']:.1f} iterations")
 
+    pagerank_leg = None
+    if not args.no_pagerank:
+        # global PageRank: FORA from the source distribution (1/n, ..., 1/n),
+        # the workload's eps, delta, p_f and k, one query per call
+        fora.pagerank(G, alpha, eps, k=k, seed=seed, ws=ws)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for _ in range(args.steps):
+            rp = fora.pagerank(G, alpha, eps, k=k, seed=seed, ws=ws, stats=True)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - tp
+        sp = rp.stats
+        pagerank_leg = dict(ms_per_query=round(dtp / args.steps * 1e3, 3),
+                            phases_ms={x: round(sp[x], 3) for x in
+                                       ("ms_push", "ms_plan", "ms_walk", "ms_topk")},
+                            rounds=sp["rounds"], edge_ops=sp["edge_ops"], walks=sp["walks"],
+                            note="source distribution (1/n, ..., 1/n), the paper's "
+                                 "extension of Algorithm 1")
+        log(f"global PageRank: {pagerank_leg['ms_per_query']} ms per query")
+
     graph_mode = None
     if graph_rounds > 0 and not args.no_graph:
         G.set_tuning(graph_rounds=graph_rounds)
@@ -365,6 +386,7 @@ def main():
         "batched_learned_rmax": learned_leg,
         "batched_alg3": alg3,
         "topk_fora": topk_leg,
+        "global_pagerank": pagerank_leg,
         "fora_plus_index": index_leg,
         "graph_replay": graph_mode,
         "tuning": tuning,

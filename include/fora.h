@@ -213,6 +213,23 @@ int fora_ssppr_batch(const fora_graph *g, int32_t batch,
                      size_t ws_bytes, int32_t *d_ids, float *d_vals,
                      fora_stats *h_stats, void *stream);
 
+/* FORA for source distributions (the paper's extension to source
+ * distributions; global PageRank is sigma = (1/n, ..., 1/n)): query b's push
+ * starts from r = sigma_b instead of e_s, which keeps the invariant
+ * pi(sigma, t) = q(t) + sum_v r(v) pi(v, t), so walks, estimate and top-k are
+ * those of fora_ssppr_batch and the eps guarantee holds for pi(sigma, .).
+ * d_sigma: double[batch][n], device, caller-owned, read once; each row a
+ * probability distribution (entries rounded to the FP32 residues; FORA_BALANCE
+ * assumes a row sums to 1). The queries' src fields are not used; walks are
+ * keyed by (0xFFFFFFFF, seed) (the index key with FORA_USE_INDEX). Same
+ * workspace, outputs and flags as fora_ssppr_batch; never replayed from a
+ * captured graph (graph_rounds is ignored). Errors: those of
+ * fora_ssppr_batch; FORA_E_ARG for a null d_sigma or an entry that is
+ * negative or not finite (reported when the call completes). */
+int fora_dist_batch(const fora_graph *g, int32_t batch, const fora_query *h_queries,
+                    const double *d_sigma, int32_t kmax, void *d_ws, size_t ws_bytes,
+                    int32_t *d_ids, float *d_vals, fora_stats *h_stats, void *stream);
+
 /* ---- step-level entry points (used to compare each phase on its own) ---- */
 
 /* ---- FORA+ walk-destination index (section 3.3) ---------------------------

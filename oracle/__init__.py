@@ -282,6 +282,55 @@ def fora(g, s: int, alpha: float = 0.2, eps: float = 0.5, delta: float | None = 
     out.update(wk)
     return out
 
+DIST_KEY0 = 0xFFFFFFFF  # first Philox key word of walks for a source distribution
+
+
+def fora_dist(g, sigma, alpha: float = 0.2, eps: float = 0.5, delta: float | None = None,
+              pf: float | None = None, k: int = 500, seed: int = 0,
+              rmax: float | None = None, log_frontiers: bool = False) -> dict:
+    """FORA for a source distribution sigma (the paper's appendix on source
+    distributions): Algorithm 1 starts from r = sigma, q = 0 instead of
+    r = e_s, which keeps the invariant pi(sigma, t) = q(t) + sum_v r(v)
+    pi(v, t); Algorithm 2 and the selection are unchanged. Global PageRank is
+    sigma = (1/n, ..., 1/n). Walks are keyed by (DIST_KEY0, seed)."""
+    n = g.n
+    delta = 1.0 / n if delta is None else delta
+    pf = 1.0 / n if pf is None else pf
+    sigma = np.asarray(sigma, np.float64)
+    if sigma.shape != (n,) or not np.all(np.isfinite(sigma)) or np.any(sigma < 0):
+        raise ValueError("sigma must be n finite non-negative values")
+    if validate(g) != 0:
+        raise ValueError("invalid graph")
+    c = constants(g.m, alpha, eps, delta, pf, rmax)
+    lib = _load()
+    rp, ci = _csr(g)
+    r = sigma.copy()
+    q = np.zeros(n, np.float64)
+    max_rounds = 100000
+    sizes = np.zeros(max_rounds, np.int32)
+    ops = np.zeros(1, np.int64)
+    margin = np.zeros(1, np.float64)
+    cap = 64 * n if log_frontiers else 0
+    flog = np.zeros(cap, np.int32) if log_frontiers else None
+    rounds = lib.oracle_push_continue(n, _p(rp), _p(ci), alpha, c["rmax"], _p(r), _p(q),
+                                      max_rounds, _p(sizes), _p(ops), _p(flog), cap, _p(margin))
+    if rounds < 0:
+        raise RuntimeError(f"oracle_push_continue failed ({rounds})")
+    sizes = sizes[:rounds].copy()
+    pv, po, pw = plan(r, c["omega_unit"])
+    wk = walks(g, DIST_KEY0, seed, c["t_alpha"], pv, po, pw)
+    pi = q + wk["acc"]
+    ids, vals = topk(pi, min(k, n))
+    out = dict(consts=c, plan=(pv, po, pw), pi=pi, topk_ids=ids, topk_vals=vals, r=r, q=q,
+               rounds=int(rounds), round_sizes=sizes, edge_ops=int(ops[0]),
+               min_margin=float(margin[0]), r_sum=float(r.sum()))
+    if log_frontiers:
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        out["frontiers"] = [flog[offs[i]:offs[i + 1]].copy() for i in range(rounds)]
+    out.update(wk)
+    return out
+
+
 def topk_deltas(n: int, k: int):
     """Algorithm 5's thresholds: delta = 1/k, 1/(2k), ... while above 1/n,
     then 1/n (the last iteration returns whatever it finds)."""

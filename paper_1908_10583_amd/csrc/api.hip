@@ -90,9 +90,10 @@ struct PinnedSlot {
   }
 };
 
-int check_query(const fora_graph* g, const fora_query& q) {
+// dist: the query's source is a distribution (its src field is not used)
+int check_query(const fora_graph* g, const fora_query& q, bool dist = false) {
   const int32_t n = g->dev.n;
-  if (q.src < 0 || q.src >= n) return fail(FORA_E_ARG, "source out of range");
+  if (!dist && (q.src < 0 || q.src >= n)) return fail(FORA_E_ARG, "source out of range");
   if (!(q.alpha > 0.0 && q.alpha < 1.0)) return fail(FORA_E_ARG, "alpha must be in (0,1)");
   if (!(q.eps > 0.0 && q.eps < 1.0)) return fail(FORA_E_ARG, "eps must be in (0,1)");
   if (!(q.delta > 0.0 && q.delta <= 1.0)) return fail(FORA_E_ARG, "delta must be in (0,1]");
@@ -118,7 +119,7 @@ int check_query(const fora_graph* g, const fora_query& q) {
 //   omega_unit = (2 eps/3 + 2) ln(2/p_f) / (eps^2 delta)
 //   r_max      = eps / sqrt(m) * sqrt(delta / ((2 eps/3 + 2) ln(2/p_f))),
 //                or eps^2 delta / ((2 eps/3 + 2) ln(2/p_f)) when m r_max > 1.
-QueryDev plan_query(const fora_graph* g, const fora_query& q) {
+QueryDev plan_query(const fora_graph* g, const fora_query& q, bool dist = false) {
   QueryDev d{};
   const double c = 2.0 * q.eps / 3.0 + 2.0;
   const double L = std::log(2.0 / q.pf);
@@ -131,8 +132,9 @@ QueryDev plan_query(const fora_graph* g, const fora_query& q) {
   d.alpha = q.alpha;
   d.src = q.src;
   d.k = q.k;
-  d.key0 = (uint32_t)q.src;
+  d.key0 = dist ? kDistKey0 : (uint32_t)q.src;
   d.key1 = (uint32_t)(q.seed & 0xFFFFFFFFull);
+  if (dist) d.src = 0;
   d.t_alpha = (uint32_t)std::floor(std::ldexp(q.alpha, 32));
   d.flags = q.flags;
   d.walk_cost = (q.flags & FORA_BALANCE) ? q.walk_cost : 0.0;
@@ -144,6 +146,8 @@ QueryDev plan_query(const fora_graph* g, const fora_query& q) {
 }
 
 int error_code_from_flags(int flags) {
+  if (flags & kErrBadDist)
+    return fail(FORA_E_ARG, "source distribution entries must be finite and non-negative");
   if (flags & kErrBadPlan)
     return fail(FORA_E_ARG, "walk plan nodes must be strictly increasing ids in [0, n)");
   if (flags & kErrOmegaOverflow)
@@ -383,9 +387,10 @@ int run_queries_graph(fora_graph* g, const Call& c, int batch, const std::vector
   return finish(g, c, batch, s, h_stats, qd, nullptr);
 }
 
+// d_sigma (nullable): double[batch][n], each query's source distribution
 int run_queries(fora_graph* g, int batch, const fora_query* qs, int kmax, void* d_ws,
                 size_t ws_bytes, int32_t* d_ids, float* d_vals, fora_stats* h_stats,
-                hipStream_t s) {
+                hipStream_t s, const double* d_sigma = nullptr) {
   if (!qs) return fail(FORA_E_ARG, "null queries");
   if (!d_ids || !d_vals) return fail(FORA_E_ARG, "null output");
   Call c;
@@ -394,23 +399,26 @@ int run_queries(fora_graph* g, int batch, const fora_query* qs, int kmax, void* 
   std::vector<QueryDev> qd(batch);
   bool all_index = true;
   for (int b = 0; b < batch; ++b) {
-    rc = check_query(g, qs[b]);
+    rc = check_query(g, qs[b], d_sigma != nullptr);
     if (rc != FORA_OK) return rc;
     if (qs[b].k > kmax) return fail(FORA_E_ARG, "kmax smaller than a query's k");
-    qd[b] = plan_query(g, qs[b]);
+    qd[b] = plan_query(g, qs[b], d_sigma != nullptr);
     all_index = all_index && (qs[b].flags & FORA_USE_INDEX);
   }
   c.walk_chunk = all_index ? std::max(walk_chunk(g), kIndexWalkChunk) : walk_chunk(g);
   c.index_only = all_index;
   FORA_HIP(hipSetDevice(g->device));
-  if (g->tuning.graph_rounds > 0)
+  if (g->tuning.graph_rounds > 0 && !d_sigma)
     return run_queries_graph(g, c, batch, qd, kmax, d_ws, d_ids, d_vals, h_stats, s);
   FORA_HIP(launch_fill_zero((char*)d_ws + c.L.zero_begin, c.L.zero_end - c.L.zero_begin, s));
   FORA_HIP(hipMemcpyAsync(c.w.queries, qd.data(), sizeof(QueryDev) * batch,
                           hipMemcpyHostToDevice, s));
   PhaseEvents pe(h_stats != nullptr);
   pe.mark(0, s);
-  FORA_HIP(launch_init_queries(g->dev, c.w, batch, s));
+  if (d_sigma)
+    FORA_HIP(launch_init_dist(g->dev, c.w, c.L, batch, d_sigma, s));
+  else
+    FORA_HIP(launch_init_queries(g->dev, c.w, batch, s));
   rc = run_push(g, c, batch, s, true, nullptr, 0, nullptr);
   if (rc != FORA_OK) return rc;
   pe.mark(1, s);
@@ -852,6 +860,15 @@ int fora_ssppr_batch(const fora_graph* g, int32_t batch, const fora_query* h_que
   if (kmax < 1 || kmax > FORA_MAX_K) return fail(FORA_E_ARG, "kmax out of range");
   return run_queries(const_cast<fora_graph*>(g), batch, h_queries, kmax, d_ws, ws_bytes, d_ids,
                      d_vals, h_stats, (hipStream_t)stream);
+}
+
+int fora_dist_batch(const fora_graph* g, int32_t batch, const fora_query* h_queries,
+                    const double* d_sigma, int32_t kmax, void* d_ws, size_t ws_bytes,
+                    int32_t* d_ids, float* d_vals, fora_stats* h_stats, void* stream) {
+  if (kmax < 1 || kmax > FORA_MAX_K) return fail(FORA_E_ARG, "kmax out of range");
+  if (!d_sigma) return fail(FORA_E_ARG, "null source distributions");
+  return run_queries(const_cast<fora_graph*>(g), batch, h_queries, kmax, d_ws, ws_bytes, d_ids,
+                     d_vals, h_stats, (hipStream_t)stream, d_sigma);
 }
 
 int fora_build_index(fora_graph* g, double alpha, double walks_per_degree, uint32_t key0,

@@ -50,6 +50,7 @@ enum : int {
   kErrGraphDangling = 32,
   kErrTopk = 64,
   kErrBadPlan = 128,
+  kErrBadDist = 256,  // a source distribution entry is negative or not finite
 };
 
 struct QueryDev {
@@ -218,6 +219,10 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_graph_check(const GraphDev& g, int* d_flags, int* d_maxdeg, int* d_hubs,
                               int2* info, hipStream_t s);
 hipError_t launch_init_queries(const GraphDev& g, const Ws& w, int batch, hipStream_t s);
+// r = sigma (double[batch][n], rounded to FP32), then the round-0 frontier
+hipError_t launch_init_dist(const GraphDev& g, const Ws& w, const Layout& L, int batch,
+                            const double* sigma, hipStream_t s);
+constexpr uint32_t kDistKey0 = 0xFFFFFFFFu;  // first walk key word of a source distribution
 hipError_t launch_push_round(const GraphDev& g, const Ws& w, const Layout& L, int batch,
                              int t, int blocks, int pull_ratio, int32_t* frontier_log,
                              int64_t log_cap, hipStream_t s);

@@ -90,6 +90,38 @@ hipError_t launch_init_queries(const GraphDev& g, const Ws& w, int batch, hipStr
   return hipGetLastError();
 }
 
+// Source distributions (the paper's extension of Algorithm 1): the initial
+// residue is sigma instead of e_s; q starts at zero (the zero-filled rows).
+__global__ void k_init_dist(const double* __restrict__ sigma, const QueryDev* Q, int batch,
+                            int n, float* r, Ctrl* ctrl, int32_t* stop, StatSlot* slots) {
+  const u64 total = (u64)batch * (u64)n;
+  bool bad = false;
+  for (u64 gi = (u64)blockIdx.x * blockDim.x + threadIdx.x; gi < total;
+       gi += (u64)gridDim.x * blockDim.x) {
+    const double x = sigma[gi];
+    const bool ok = x >= 0.0 && isfinite(x);
+    bad |= !ok;
+    r[gi] = ok ? (float)x : 0.0f;
+  }
+  if (bad) atomicOr(&ctrl->error, kErrBadDist);
+  const u64 b = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < (u64)batch && (Q[b].flags & FORA_BALANCE) && balance_met(Q[b], 0, 0.0)) {
+    stop[b] = 1;
+    slots[b * kStatSlots].balance_stopped = 1;
+  }
+}
+
+hipError_t launch_init_dist(const GraphDev& g, const Ws& w, const Layout& L, int batch,
+                            const double* sigma, hipStream_t s) {
+  const u64 total = (u64)batch * (u64)g.n;
+  const int blocks = (int)std::min<u64>(std::max<u64>((total + 255) / 256, 1), 16384);
+  k_init_dist<<<blocks, 256, 0, s>>>(sigma, w.queries, batch, g.n, w.r, w.ctrl, w.stop,
+                                     w.qstats);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_seed_frontier(g, w, L, batch, 0, s);
+}
+
 // Per-query counters are staged in LDS (dynamic: 12 bytes per query) and
 // added to the block's stat slot and to this round's frontier-edge slot.
 __global__ __launch_bounds__(256) void k_push_snapshot(

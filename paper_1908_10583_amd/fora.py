@@ -89,6 +89,8 @@ def _load():
                         ctypes.POINTER(fora_stats), P], ctypes.c_int),
         "fora_ssppr_batch": ([P, I32, ctypes.POINTER(fora_query), I32, P, SZ, P, P,
                               ctypes.POINTER(fora_stats), P], ctypes.c_int),
+        "fora_dist_batch": ([P, I32, ctypes.POINTER(fora_query), P, I32, P, SZ, P, P,
+                             ctypes.POINTER(fora_stats), P], ctypes.c_int),
         "fora_build_index": ([P, F64, F64, ctypes.c_uint32, ctypes.c_uint32, P], ctypes.c_int),
         "fora_index_info": ([P, ctypes.POINTER(I64), ctypes.POINTER(F64), ctypes.POINTER(F64),
                              ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)],
@@ -126,6 +128,7 @@ _lib = _load()
 EXPORTED = ["fora_last_error", "fora_build_csr", "fora_free_graph", "fora_graph_info",
             "fora_get_tuning", "fora_set_tuning",
             "fora_workspace_size", "fora_workspace_views", "fora_ssppr", "fora_ssppr_batch",
+            "fora_dist_batch",
             "fora_push_only", "fora_walk_only", "fora_philox", "fora_features",
             "fora_mlp_forward", "fora_mlp_backward", "fora_adam_step", "fora_mlp_to_bf16",
             "fora_mlp_forward_bf16", "fora_predict_rmax", "fora_push_sweep",
@@ -330,6 +333,40 @@ def fora_ssppr_batch(g: Graph, queries, kmax: int | None = None,
     _check(_lib.fora_ssppr_batch(g.handle, B, queries, kmax, _ptr(ws), ws.numel(), _ptr(ids),
                                  _ptr(vals), st, ctypes.c_void_p(_stream(stream))))
     return Result(ids, vals, [s.as_dict() for s in st] if st is not None else None)
+
+
+def fora_dist_batch(g: Graph, queries, sigma: torch.Tensor, kmax: int | None = None,
+                    ws: torch.Tensor | None = None, stats: bool = False,
+                    out: tuple | None = None, stream=None) -> Result:
+    """FORA for source distributions: query b starts from r = sigma[b]
+    (float64 [batch, n] on the graph's device); the queries' src fields are
+    not used."""
+    B = len(queries)
+    sigma = sigma.to(device=g.device, dtype=torch.float64).contiguous()
+    if tuple(sigma.shape) != (B, g.n):
+        raise ValueError(f"sigma must have shape ({B}, {g.n})")
+    kmax = max(q.k for q in queries) if kmax is None else kmax
+    ws = workspace(g, B) if ws is None else ws
+    if out is None:
+        ids = torch.empty((B, kmax), dtype=torch.int32, device=g.device)
+        vals = torch.empty((B, kmax), dtype=torch.float32, device=g.device)
+    else:
+        ids, vals = out
+    st = (fora_stats * B)() if stats else None
+    _check(_lib.fora_dist_batch(g.handle, B, queries, _ptr(sigma), kmax, _ptr(ws), ws.numel(),
+                                _ptr(ids), _ptr(vals), st, ctypes.c_void_p(_stream(stream))))
+    return Result(ids, vals, [s.as_dict() for s in st] if st is not None else None)
+
+
+def pagerank(g: Graph, alpha: float = 0.2, eps: float = 0.5, delta: float | None = None,
+             pf: float | None = None, k: int = 500, seed: int = 0, flags: int = 0,
+             ws: torch.Tensor | None = None, stats: bool = False) -> Result:
+    """Global PageRank with FORA: the source distribution (1/n, ..., 1/n)."""
+    qs = make_queries([0], alpha=alpha, eps=eps, delta=delta, pf=pf, k=k, seed=seed, n=g.n,
+                      flags=flags)
+    sigma = torch.full((1, g.n), 1.0 / g.n, dtype=torch.float64, device=g.device)
+    r = fora_dist_batch(g, qs, sigma, kmax=k, ws=ws, stats=stats)
+    return Result(r.ids[0], r.vals[0], r.stats[0] if stats else None)
 
 
 def fora_build_index(g: Graph, alpha: float, walks_per_degree: float, key0: int, key1: int,
