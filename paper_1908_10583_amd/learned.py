@@ -321,7 +321,9 @@ def main(argv=None):
             if f.startswith(f"{args.workload}_sweep_") and f.endswith(".npz"):
                 a, b = (int(x) for x in f[:-4].split("_")[-2:])
                 z = np.load(os.path.join(sd, f), allow_pickle=False)
-                if b <= len(tr) and np.array_equal(z["srcs"], tr[a:b]):
+                # pieces of another threshold grid are swept again
+                if b <= len(tr) and np.array_equal(z["srcs"], tr[a:b]) and \
+                        z["E"].shape[1] == len(MULTS):
                     E[a:b], W[a:b], have[a:b] = z["E"], z["W"], True
     for a in range(0, len(tr), 1024):
         b = min(a + 1024, len(tr))

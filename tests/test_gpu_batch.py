@@ -182,6 +182,18 @@ def test_many_pulling_queries_match_single_calls(g1k, G1k):
     assert bat.stats[0]["rounds"] == ref["rounds"]
 
 
+def test_a_workspace_fits_every_smaller_batch(g1k, G1k):
+    # the pull groups change with the batch (1, 4 or 16 queries), the
+    # workspace size must not shrink with it: top-k FORA runs its later
+    # iterations on the first one's workspace with fewer queries
+    sizes = [fora.fora_workspace_size(G1k, b) for b in range(1, 41)]
+    assert all(a <= b for a, b in zip(sizes, sizes[1:]))
+    ws = fora.workspace(G1k, 16)
+    qs = fora.make_queries(list(range(15)), k=10, seed=1, n=g1k.n)
+    res = fora.fora_ssppr_batch(G1k, qs, ws=ws, stats=True)
+    assert all(s["walks"] > 0 for s in res.stats)
+
+
 def test_autotune_sets_and_caches(g1k, G1k, tmp_path):
     qs = fora.make_queries([0, 1, 2, 3], k=50, n=g1k.n)
     path = str(tmp_path / "tune.json")
