@@ -299,7 +299,8 @@ hipError_t launch_degree_rank(const GraphDev& g, int32_t* rank, void* scratch,
 
 // Walk records (see GraphDev): record lengths in 8-byte units, their
 // exclusive prefix (the record starts), then one wavefront per node fills a
-// record: lane 0 the header, all lanes the neighbours' record starts.
+// record: lane 0 the header, all lanes the neighbours' slots (record start,
+// degree and, where the graph's sizes allow, id).
 __global__ void k_rec_len(const int2* __restrict__ info, const int32_t* __restrict__ rank,
                           int32_t n, int32_t* len) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
