@@ -146,7 +146,9 @@ typedef struct fora_tuning {
                                  id fit 64 bits, so no header is read where a
                                  walk stops; 0: (start, degree) slots only.
                                  Changing it rebuilds the records (waits for
-                                 the device; same results)                       */
+                                 the device; same results). FORA_E_NOMEM then
+                                 leaves the graph as it was; FORA_E_HIP leaves
+                                 it unusable (free it)                           */
 } fora_tuning;
 
 const char *fora_last_error(void);
@@ -238,6 +240,8 @@ int fora_dist_batch(const fora_graph *g, int32_t batch, const fora_query *h_quer
  * walks_per_degree = r_max omega_unit) keyed by (key0, key1) and walk index,
  * stopping with probability alpha; their end points are stored in (v, j)
  * order. Allocates the index (8 (n + 1) + 4 sum omega_max bytes) and waits.
+ * Replacing an index drops the handle's captured graphs; not thread-safe
+ * against concurrent query calls on the same handle.
  * FORA_E_OVERFLOW if some omega_max(v) >= 2^32. */
 int fora_build_index(fora_graph *g, double alpha, double walks_per_degree, uint32_t key0,
                      uint32_t key1, void *stream);

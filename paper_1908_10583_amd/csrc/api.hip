@@ -644,22 +644,15 @@ int build_records(fora_graph* g, bool with_ids, hipStream_t s) {
   while ((1ll << qb) < units) ++qb;  // record starts are below n + m
   while ((1ll << ib) < n) ++ib;      // ids are below n
   const int db = 64 - qb - ib;
-  if (!with_ids) {
-    g->dev.slot_qbits = 32;
-    g->dev.slot_dbits = 32;
-    g->dev.slot_ids = 0;
-  } else if (db >= 1 && db <= 32 && (int64_t)g->dev.max_deg < (1ll << db)) {
-    g->dev.slot_qbits = qb;
-    g->dev.slot_dbits = db;
-    g->dev.slot_ids = 1;
-  } else if (db > 32) {  // small graphs: a 32-bit degree field always fits
-    g->dev.slot_qbits = qb;
-    g->dev.slot_dbits = 32;
-    g->dev.slot_ids = 1;
-  } else {
-    g->dev.slot_qbits = 32;
-    g->dev.slot_dbits = 32;
-    g->dev.slot_ids = 0;
+  // the slot format, applied to the graph only once the scratch is there
+  int fq = 32, fd = 32, fid = 0;
+  if (with_ids && db >= 1 && db <= 32 && (int64_t)g->dev.max_deg < (1ll << db)) {
+    fq = qb;
+    fd = db;
+    fid = 1;
+  } else if (with_ids && db > 32) {  // small graphs: a 32-bit degree field always fits
+    fq = qb;
+    fid = 1;
   }
   const int64_t tiles = (n + 2047) / 2048;
   int32_t* tmp = nullptr;
@@ -678,6 +671,9 @@ int build_records(fora_graph* g, bool with_ids, hipStream_t s) {
   }
   g->dev.rec = g->rec_owned;
   g->dev.rec_q = g->rec_q_owned;
+  g->dev.slot_qbits = fq;
+  g->dev.slot_dbits = fd;
+  g->dev.slot_ids = fid;
   hipError_t e = launch_build_records(g->dev, g->rec_q_owned, g->rec_owned, tmp, tsum, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   release();
