@@ -19,9 +19,9 @@ import torch
 from . import fora
 
 PULL_RATIOS = (0, 4, 16, 64, 256)
-PUSH_BLOCKS = (2, 4, 8, 16)
-WALK_BLOCKS = (4, 8, 12, 16)
-WALK_CHUNKS = (256, 512, 1024, 2048)
+PUSH_BLOCKS = (2, 4, 8, 16, 32)
+WALK_BLOCKS = (2, 4, 8, 12, 16)
+WALK_CHUNKS = (256, 512, 1024, 2048, 4096)
 WALK_AGG = (0, 1)
 
 

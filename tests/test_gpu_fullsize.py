@@ -36,7 +36,7 @@ from paper_1908_10583_amd import fora  # noqa: E402
 
 ALPHA, EPS, K, SEED = 0.2, 0.5, 500, 0
 # the launch configuration the autotuner picks for this workload on MI355X
-BENCH_TUNING = dict(walk_blocks_per_cu=4, walk_chunk=2048, push_blocks_per_cu=16,
+BENCH_TUNING = dict(walk_blocks_per_cu=4, walk_chunk=4096, push_blocks_per_cu=32,
                     graph_rounds=62, pull_ratio=64, record_ids=1, walk_agg=0)
 SAMPLED = (0, 37, 99)
 
