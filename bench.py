@@ -93,7 +93,8 @@ def main():
                          "readings calibrate FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "a single-GPU benchmark: --gpus must be 1 (queries shard "
+                                   "across GPUs by source, with no collective on the hot path)"}))
         sys.exit(2)
 
     import torch

@@ -28,9 +28,9 @@
  *     integers here).
  *
  * Parity pins: see the tests. The Philox block function itself is
- * "parity unpinned" against the published known-answer vectors (none are
- * available to this build); it is pinned only statistically and through the
- * walk distributions it induces.
+ * "parity unpinned" against the published known-answer vectors (they are
+ * not reproduced in this repository); it is pinned only statistically and
+ * through the walk distributions it induces.
  */
 #include <math.h>
 #include <stdint.h>
