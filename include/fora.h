@@ -142,9 +142,13 @@ typedef struct fora_tuning {
   int32_t walk_agg;           /* 1: waves sum walk end points in LDS before
                                  adding them to HBM (same results)               */
   int32_t record_ids;         /* 1 (default): a walk-record slot also holds the
-                                 neighbour's id where record start, degree and
-                                 id fit 64 bits, so no header is read where a
-                                 walk stops; 0: (start, degree) slots only.
+                                 neighbour's id where record start, a degree
+                                 field of 12 bits or more, and id fit 64 bits,
+                                 so no header is read where a walk stops
+                                 (degrees too wide for the field are read from
+                                 the header of the node reached); 0: (start,
+                                 degree) slots only; 2: ids with a 4-bit
+                                 degree field (exercises the header reads).
                                  Changing it rebuilds the records (waits for
                                  the device; same results). FORA_E_NOMEM then
                                  leaves the graph as it was; FORA_E_HIP leaves

@@ -637,21 +637,33 @@ int build_rank(fora_graph* g, hipStream_t s) {
 // record starts fit 32 bits. A slot also carries the neighbour's id when
 // record start, degree and id fit 64 bits together (for example n = 2^20,
 // m = 1.7e7: 25 + 19 + 20 bits).
-int build_records(fora_graph* g, bool with_ids, hipStream_t s) {
+// mode: the tuning's record_ids (0: (start, degree) slots; 1: ids where
+// they fit; 2: ids with a 4-bit degree field, which sends every degree of
+// 15 or more to the header)
+int build_records(fora_graph* g, int mode, hipStream_t s) {
   const int64_t n = g->dev.n;
   const int64_t units = g->dev.m + n;
   int qb = 1, ib = 1;
   while ((1ll << qb) < units) ++qb;  // record starts are below n + m
   while ((1ll << ib) < n) ++ib;      // ids are below n
   const int db = 64 - qb - ib;
-  // the slot format, applied to the graph only once the scratch is there
+  // The slot format, applied to the graph only once the scratch is there.
+  // A degree the field cannot hold is stored as all ones and read from the
+  // node's header by the walk; with a field of at least kMinDegBits bits that
+  // happens only for hubs, whose headers stay in L2.
+  constexpr int kMinDegBits = 12;
   int fq = 32, fd = 32, fid = 0;
-  if (with_ids && db >= 1 && db <= 32 && (int64_t)g->dev.max_deg < (1ll << db)) {
+  const bool all_fit = db >= 1 && db <= 32 && (int64_t)g->dev.max_deg < (1ll << db) - 1;
+  if (mode == 1 && db > 32) {  // small graphs: a 32-bit degree field always fits
+    fq = qb;
+    fid = 1;
+  } else if (mode == 1 && (all_fit || (db >= kMinDegBits && db <= 32))) {
     fq = qb;
     fd = db;
     fid = 1;
-  } else if (with_ids && db > 32) {  // small graphs: a 32-bit degree field always fits
+  } else if (mode == 2 && db >= 4) {
     fq = qb;
+    fd = 4;
     fid = 1;
   }
   const int64_t tiles = (n + 2047) / 2048;
@@ -745,7 +757,7 @@ int fora_build_csr(int32_t n, int64_t m, const int32_t* d_rowptr, const int32_t*
   g->dev.n_hubs = host_flags[2];
   int rrc = build_rank(g, s);
   if (rrc == FORA_OK) rrc = build_reverse(g, s);
-  if (rrc == FORA_OK) rrc = build_records(g, g->tuning.record_ids != 0, s);
+  if (rrc == FORA_OK) rrc = build_records(g, g->tuning.record_ids, s);
   if (rrc != FORA_OK) {
     const std::string msg = g_err;
     return cleanup(rrc, msg);
@@ -772,13 +784,13 @@ int fora_set_tuning(fora_graph* g, const fora_tuning* t) {
     return fail(FORA_E_ARG, "graph_rounds must be in [0, 4096]");
   if (t->pull_ratio < 0) return fail(FORA_E_ARG, "pull_ratio must be >= 0");
   if (t->walk_agg != 0 && t->walk_agg != 1) return fail(FORA_E_ARG, "walk_agg must be 0 or 1");
-  if (t->record_ids != 0 && t->record_ids != 1)
-    return fail(FORA_E_ARG, "record_ids must be 0 or 1");
+  if (t->record_ids < 0 || t->record_ids > 2)
+    return fail(FORA_E_ARG, "record_ids must be 0, 1 or 2");
   drop_graphs(g);
   if (t->record_ids != g->tuning.record_ids) {
     FORA_HIP(hipSetDevice(g->device));
     FORA_HIP(hipDeviceSynchronize());  // no call may still read the records
-    const int rc = build_records(g, t->record_ids != 0, nullptr);
+    const int rc = build_records(g, t->record_ids, nullptr);
     if (rc != FORA_OK) return rc;
   }
   g->tuning = *t;

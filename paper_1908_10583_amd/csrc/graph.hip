@@ -327,9 +327,11 @@ __global__ void k_fill_rec(const int2* __restrict__ info, const int32_t* __restr
     const int2 inf = info[v];
     u64* r = rec + rec_q[v];
     if (lane == 0) r[0] = (u64)(uint32_t)inf.y | ((u64)(uint32_t)v << 32);
+    const u64 dmask = (1ull << dbits) - 1;  // all ones: the degree is in the header
     for (int i = lane; i < inf.y; i += 64) {
       const int32_t u = colidx[(int64_t)inf.x + i];
-      u64 slot = (u64)rec_q[u] | ((u64)(uint32_t)info[u].y << qbits);
+      const u64 d = (u64)(uint32_t)info[u].y;
+      u64 slot = (u64)rec_q[u] | ((d < dmask ? d : dmask) << qbits);
       if (ids) slot |= (u64)(uint32_t)u << (qbits + dbits);
       r[1 + i] = slot;
     }

@@ -114,10 +114,11 @@ struct GraphDev {
   // walk records: node v's record starts at 8-byte unit rec_q[v]; unit 0
   // is the header d(v) | v << 32, then one unit per out-neighbour u in CSR
   // order holding rec_q[u] in bits [0, slot_qbits) and d(u) in the next
-  // slot_dbits bits, so a move reads the next node's record start and degree
-  // in one load. With slot_ids, u itself sits in the bits above them and the
-  // header is never read; otherwise the fields are 32 bits each and a walk
-  // reads its end node's id from the header.
+  // slot_dbits bits (all ones if d(u) does not fit: then it is read from u's
+  // header), so a move reads the next node's record start and degree in one
+  // load. With slot_ids, u itself sits in the bits above them and no header
+  // is read where a walk stops; otherwise the fields are 32 bits each and a
+  // walk reads its end node's id from the header.
   const u64* rec;
   const uint32_t* rec_q;
   int32_t slot_qbits;

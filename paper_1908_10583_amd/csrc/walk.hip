@@ -27,7 +27,8 @@
 // the current record, which holds the chosen neighbour's record start and
 // out-degree (and its id, where the graph's sizes let the three fit), so
 // each move is one dependent load. Without ids in the slots, the end node's
-// id is read from its record's header where the walk stops.
+// id is read from its record's header where the walk stops; a degree too
+// wide for its field (a hub's) is read from the header when it is reached.
 //
 // Schedule: a persistent grid; each wavefront takes chunks of `chunk`
 // consecutive walk ids from a device work queue and keeps all 64 lanes busy:
@@ -273,6 +274,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(
         const u64 u = rec[(size_t)q + 1 + idx];
         q = (uint32_t)(u & qmask);
         deg = (uint32_t)((u >> qbits) & dmask);
+        if (deg == (uint32_t)dmask) deg = (uint32_t)rec[q];  // too wide: the header's
         if (slot_ids) x = (int32_t)(u >> ishift);
         ++step;
         forced = false;

@@ -238,19 +238,20 @@ def test_walk_parity_oracle_plan(g1k, G1k):
 
 @pytest.mark.parametrize("seed", [0, 1])
 def test_walk_parity_both_record_forms(grmat12, Grmat12, seed):
-    # slots with the neighbour's id (the default where it fits, as here) and
-    # (start, degree) slots with the id read from the end node's header
+    # slots with the neighbour's id (the default where it fits, as here),
+    # (start, degree) slots with the id read from the end node's header, and
+    # ids with a 4-bit degree field (degrees of 15 or more from the header)
     pv, po, pw = synth.random_walk_plan(grmat12, 2000, 500, 40 + seed)
     t0 = Grmat12.get_tuning()
     assert t0["record_ids"] == 1
     try:
-        for form in (0, 1):
+        for form in (0, 1, 2):
             Grmat12.set_tuning(record_ids=form)
             _walk_compare(grmat12, Grmat12, pv, po, pw, 5 + seed, 6)
     finally:
         Grmat12.set_tuning(**t0)
     with pytest.raises(fora.FORAError) as ei:
-        Grmat12.set_tuning(record_ids=2)
+        Grmat12.set_tuning(record_ids=3)
     assert ei.value.code == fora.FORA_E_ARG
 
 
