@@ -1,11 +1,12 @@
 """Learned per-source r_max.
 
-For each training source the library pushes once through 12 thresholds
-r_i = mult_i * r_max* (mult from 8 down to 1/4, log-spaced; each threshold
+For each training source the library pushes once through 16 thresholds
+r_i = mult_i * r_max* (mult from 8 down to 1/32, log-spaced; each threshold
 continues from the previous one's state) and records the exact push work
 E_i (residue increments) and the walk count W_i Algorithm 2 would then run.
-Costs are priced with per-unit push and walk times measured on this GPU
-(full FORA calls at several r_max, timed by the library's phase events), so
+Costs are priced with marginal per-unit push and walk times measured on this
+GPU (the slopes of each phase's time against its work over batched FORA
+calls at several r_max, timed by the library's phase events), so
 label(s) = ln(mult of the cheapest threshold). A 7 -> 64 -> 64 -> 1 GELU MLP
 is trained on (features, label) with the library's own forward, backward and
 Adam kernels; inference runs the library's BF16 kernel, which maps the
