@@ -194,6 +194,27 @@ def test_a_workspace_fits_every_smaller_batch(g1k, G1k):
     assert all(s["walks"] > 0 for s in res.stats)
 
 
+def test_maximum_batch(g1k, G1k):
+    # FORA_MAX_BATCH queries in one call (256 pull groups of 16, the
+    # per-query LDS staging at its largest); rows spot-checked against the
+    # same queries run alone, and one query more is rejected
+    B = fora.FORA_MAX_BATCH
+    srcs = [int(x) for x in np.arange(B) % g1k.n]
+    kw = dict(k=10, n=g1k.n, delta=1e-2, pf=1e-2)
+    qs = fora.make_queries(srcs, seed=list(range(B)), **kw)
+    res = fora.fora_ssppr_batch(G1k, qs, stats=True)
+    assert all(s["walks"] > 0 and s["term_violations"] == 0 for s in res.stats)
+    for b in (0, 1234, B - 1):
+        one = fora.fora_ssppr(G1k, srcs[b], k=10, seed=b, delta=1e-2, pf=1e-2, stats=True)
+        assert one.stats["rounds"] == res.stats[b]["rounds"]
+        assert one.stats["omega_unit"] == res.stats[b]["omega_unit"]
+        same = set(one.ids.cpu().numpy().tolist()) & set(res.ids[b].cpu().numpy().tolist())
+        assert len(same) >= 8
+    with pytest.raises(fora.FORAError) as ei:
+        fora.fora_ssppr_batch(G1k, fora.make_queries(srcs + [0], seed=0, **kw))
+    assert ei.value.code == fora.FORA_E_ARG
+
+
 def test_autotune_sets_and_caches(g1k, G1k, tmp_path):
     qs = fora.make_queries([0, 1, 2, 3], k=50, n=g1k.n)
     path = str(tmp_path / "tune.json")
