@@ -225,11 +225,13 @@ def main():
     alg3 = None
     if not args.no_alg3:
         # Algorithm 3 (zero-hop pruning + push/walk balance): one walk's cost in
-        # residue increments from this run's own phase timers, r_max floor
-        # r_max* / 32 so that the balance rule ends the push
-        push_unit = ph["ms_push"] / max(1, sum(s["edge_ops"] for s in stats0))
-        walk_unit = ph["ms_walk"] / max(1, sum(s["walks"] for s in stats0))
-        wc = walk_unit / push_unit
+        # residue increments, the ratio of this GPU's marginal per-walk and
+        # per-increment times (the rule weighs the walks still to come against
+        # further pushing; averages over a whole query under-price walks), r_max
+        # floor r_max* / 32 so that the balance rule ends the push
+        from paper_1908_10583_amd import learned
+        cal = learned.calibrate(G, srcs[:min(64, B)], alpha=alpha, eps=eps)
+        wc = cal["ms_per_walk"] / cal["ms_per_edge_op"]
         rstar = stats0[0]["rmax"]
         q3 = [fora.make_queries(srcs[a:b], alpha=alpha, eps=eps, k=k, seed=seed, n=g.n,
                                 rmax=rstar / 32, flags=fora.FORA_PRUNE_ZERO_HOP |
