@@ -319,7 +319,8 @@ def main(argv=None):
         srv = Server(G, slots=1, max_batch=1, mem_budget=fora.fora_workspace_size(G, 1))
         r = run_trace(srv, [dict(x, t=0.0)])[0]
         alone_ms.setdefault(str(x["eps"]), []).append(r.latency * 1e3)
-    log(f"alone: {json.dumps({k: float(np.median(v)) for k, v in alone_ms.items()})}")
+    if alone_ms:
+        log(f"alone: {json.dumps({k: float(np.median(v)) for k, v in alone_ms.items()})}")
     free, total = torch.cuda.mem_get_info(G.device)
     budget = int(args.mem_frac * free)
     for qps in (float(x) for x in args.qps.split(",")):

@@ -275,6 +275,8 @@ def poisson_requests(count: int, qps: float, sources: np.ndarray, seed: int,
     ``qps`` (exponential gaps), a source drawn uniformly from ``sources``, and
     eps and k each drawn uniformly from their choices. Returns a list of dicts
     (id, t, src, eps, k, seed)."""
+    if count <= 0:
+        return []
     rng = np.random.Generator(np.random.PCG64(seed))
     gaps = rng.exponential(1.0 / qps, size=count)
     t = np.cumsum(gaps) - gaps[0]

@@ -80,3 +80,7 @@ def test_runner_errors_reach_the_requests():
     reqs = serve.run_trace(srv, synth.poisson_requests(5, 500.0, np.arange(5), seed=5))
     assert all(r.error and "device failure" in r.error for r in reqs)
     assert serve.summarize(reqs, srv)["errors"] == 5
+
+
+def test_an_empty_trace_is_empty():
+    assert synth.poisson_requests(0, 1.0, np.arange(5), seed=1) == []
