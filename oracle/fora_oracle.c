@@ -27,10 +27,9 @@
  *     floor(U * d / 2^64) (Lemire's multiply-shift, computed with 128-bit
  *     integers here).
  *
- * Parity pins: see the tests. The Philox block function itself is
- * "parity unpinned" against the published known-answer vectors (they are
- * not reproduced in this repository); it is pinned only statistically and
- * through the walk distributions it induces.
+ * Parity pins: see the tests. The Philox block function is pinned word for
+ * word against rocRAND's independent implementation of Philox4x32-10 (run
+ * on the host), besides the statistics of the walk distributions it drives.
  */
 #include <math.h>
 #include <stdint.h>
