@@ -9,9 +9,13 @@
  *    fora_last_error() gives a message for the calling thread's last failure.
  *  - "d_" pointers are device (HBM) pointers, "h_" pointers host pointers.
  *  - Device memory for inputs, outputs and the per-call workspace is owned by
- *    the caller; the hot-path calls never allocate. Only fora_build_csr
- *    allocates (a derived per-node table of 8 bytes per node), released by
- *    fora_free_graph.
+ *    the caller; the query calls allocate no device memory of their own (a
+ *    captured HIP graph holds what the runtime gives it). The graph handle
+ *    owns derived tables of about 28 n + 12 m bytes, allocated by
+ *    fora_build_csr (a per-node table, the reverse graph for pull rounds, a
+ *    degree ranking and the walk records) and released by fora_free_graph;
+ *    fora_set_tuning may rebuild the walk records and fora_build_index
+ *    allocates the index.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    The push phase checks the frontier size from the host between groups of
  *    rounds, and every query call reads its device error flags at the end, so
@@ -236,8 +240,6 @@ int fora_dist_batch(const fora_graph *g, int32_t batch, const fora_query *h_quer
                     const double *d_sigma, int32_t kmax, void *d_ws, size_t ws_bytes,
                     int32_t *d_ids, float *d_vals, fora_stats *h_stats, void *stream);
 
-/* ---- step-level entry points (used to compare each phase on its own) ---- */
-
 /* ---- FORA+ walk-destination index (section 3.3) ---------------------------
  * Builds (or replaces) the graph's index: for every node v,
  * omega_max(v) = ceil(d(v) walks_per_degree) walks (eqn:index-rwnum with
@@ -273,6 +275,8 @@ int fora_topk_workspace_size(const fora_graph *g, int32_t batch, int32_t kmax, s
 int fora_topk_batch(const fora_graph *g, int32_t batch, const fora_query *h_queries,
                     int32_t kmax, void *d_ws, size_t ws_bytes, int32_t *d_ids, float *d_vals,
                     fora_stats *h_stats, int32_t *h_iterations, double *h_delta, void *stream);
+
+/* ---- step-level entry points (used to compare each phase on its own) ---- */
 
 /* Only the push phase of fora_ssppr for one source (Algorithm 1,
  * synchronous rounds). Results in the workspace views (row 0).
