@@ -248,7 +248,9 @@ int fora_dist_batch(const fora_graph *g, int32_t batch, const fora_query *h_quer
  * order. Allocates the index (8 (n + 1) + 4 sum omega_max bytes) and waits.
  * Replacing an index drops the handle's captured graphs; not thread-safe
  * against concurrent query calls on the same handle.
- * FORA_E_OVERFLOW if some omega_max(v) >= 2^32. */
+ * FORA_E_OVERFLOW if some omega_max(v) >= 2^32 (checked first: the old
+ * index stays). Any later failure (FORA_E_NOMEM, FORA_E_HIP) leaves the
+ * handle with no index. */
 int fora_build_index(fora_graph *g, double alpha, double walks_per_degree, uint32_t key0,
                      uint32_t key1, void *stream);
 /* The index's parameters and total end points (0 if none). */
