@@ -1,0 +1,60 @@
+"""The benchmark's host logic (CPU only): it refuses more than one GPU with a
+one-line JSON message, and it takes HBM traffic from a committed counter
+record only while the kernel's sources are the ones the counters were taken
+on."""
+import hashlib
+import json
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert out.returncode == 2
+    lines = out.stdout.strip().splitlines()
+    assert len(lines) == 1 and "error" in json.loads(lines[0])
+
+
+def _tree(tmp_path, text):
+    src = tmp_path / "k.hip"
+    src.write_text(text)
+    (tmp_path / "profiles").mkdir()
+    rec = dict(sources=["k.hip"], traffic_bytes_per_launch=1234,
+               source_sha256=hashlib.sha256(b"kernel v1").hexdigest())
+    (tmp_path / "profiles" / "k_walks_w_b1_traffic.json").write_text(json.dumps(rec))
+    return src
+
+
+def test_traffic_record_is_used_while_the_sources_match(tmp_path, monkeypatch):
+    _tree(tmp_path, "kernel v1")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.recorded_traffic("k_walks", "w_b1") == (
+        1234, os.path.join("profiles", "k_walks_w_b1_traffic.json"))
+    assert bench.recorded_traffic("k_walks", "other_b1") == (None, None)
+
+
+def test_traffic_record_is_dropped_once_a_source_changes(tmp_path, monkeypatch):
+    src = _tree(tmp_path, "kernel v2")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.recorded_traffic("k_walks", "w_b1") == (None, None)
+    src.unlink()  # a missing source counts as changed
+    assert bench.recorded_traffic("k_walks", "w_b1") == (None, None)
+
+
+@pytest.mark.parametrize("path", sorted(
+    p for p in os.listdir(os.path.join(ROOT, "profiles")) if p.endswith("_traffic.json")))
+def test_committed_traffic_records_are_well_formed(path):
+    rec = json.load(open(os.path.join(ROOT, "profiles", path)))
+    assert rec["traffic_bytes_per_launch"] > 0
+    assert len(rec["source_sha256"]) == 64
+    for src in rec["sources"]:
+        assert os.path.exists(os.path.join(ROOT, src)), src
