@@ -263,6 +263,20 @@ def test_walks_are_keyed_by_start_and_index(g1k):
     assert not np.array_equal(a["endpoints"], c["endpoints"])
 
 
+def test_walk_weight_lands_at_the_end_point(g1k):
+    # Algorithm 2: a walk from v that ends at t adds v's weight to pi_hat(t);
+    # with one plan entry, the weight at each node is its end-point count
+    # times the entry's weight, and the recorded end points give the counts
+    v, W, w = 11, 5000, 0.375
+    t_alpha = oracle.constants(g1k.m, ALPHA, 0.5, 0.01, 0.01)["t_alpha"]
+    res = oracle.walks(g1k, 0, 0, t_alpha, np.array([v], np.int32),
+                       np.array([W], np.uint64), np.array([w]), endpoints=True)
+    cnt = np.bincount(res["endpoints"], minlength=g1k.n)
+    assert np.array_equal(res["cnt"], cnt)
+    assert np.count_nonzero(cnt) > 100
+    np.testing.assert_allclose(res["acc"], cnt * w, rtol=1e-12, atol=0)
+
+
 def test_walk_totals(g1k):
     c = oracle.constants(g1k.m, ALPHA, 0.5, 1e-3, 1e-3)
     res = oracle.push(g1k, 0, ALPHA, c["rmax"])
