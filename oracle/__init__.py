@@ -360,7 +360,8 @@ def fora_topk(g, s: int, k: int, alpha: float = 0.2, eps: float = 0.5, pf: float
         out = fora(g, s, alpha=alpha, eps=eps / 2, delta=d, pf=pf_it, k=k, seed=seed + i,
                    prune=prune)
         kth = float(np.float32(out["topk_vals"][k - 1]))
-        trace.append(dict(delta=d, kth=kth, bound=(1 + eps) * d))
+        trace.append(dict(delta=d, kth=kth, bound=(1 + eps) * d,
+                          omega_unit=out["consts"]["omega_unit"]))
         if kth >= (1 + eps) * d or i == len(deltas) - 1:
             break
     out = dict(out)

@@ -131,6 +131,18 @@ def test_pruned_monte_carlo_case(g1k):
     assert out["pi"][0] >= ALPHA
 
 
+def test_pruned_query_walks_move_at_least_once(g1k):
+    # with zero-hop walks pruned every walk of the query makes a forced first
+    # move and then a geometric number of further moves: 1 / alpha moves per
+    # walk on average (variance (1 - alpha) / alpha^2), against (1 - alpha) /
+    # alpha without the forced move
+    out = oracle.fora(g1k, 0, k=50, seed=4, prune=True)
+    W = out["walks"]
+    assert W > 10000
+    mean = out["steps"] / W
+    assert abs(mean - 1 / ALPHA) < 5 * math.sqrt((1 - ALPHA) / ALPHA**2 / W)
+
+
 # ---------------------------------------------------------------- balance rule
 def test_balance_limits(g1k):
     c = oracle.constants(g1k.m, ALPHA, 0.5, 1e-3, 1e-3)

@@ -33,6 +33,22 @@ def test_delta_sequence():
     assert d[0] == 1 / 500 and d[-1] == 2.0**-20 and all(b == a / 2 for a, b in zip(d[:-2], d[1:-1]))
 
 
+def test_iterations_hold_the_union_bound(g1k):
+    # Algorithm 5's guarantee (section 6.2) is a union bound: each iteration
+    # keeps every node with pi >= delta within eps/2 of its PPR except with
+    # probability p_f / (n log2(n/k)), so that over the n nodes and the
+    # log2(n/k) halvings of delta the failure probability is p_f. Lemma 2's
+    # bound at relative error eps/2, the iteration's delta and its omega_unit
+    # is that per-node probability.
+    n, k, eps, pf = g1k.n, 50, 0.5, 1.0 / g1k.n
+    out = oracle.fora_topk(g1k, 0, k, eps=eps, pf=pf, seed=1)
+    assert len(out["trace"]) >= 2
+    e2 = eps / 2
+    for it in out["trace"]:
+        fail = 2 * math.exp(-(e2**2) * it["delta"] * it["omega_unit"] / (2 + 2 * e2 / 3))
+        assert fail * n * math.log2(n / k) == pytest.approx(pf, rel=1e-9)
+
+
 @pytest.mark.parametrize("k", [5, 50])
 def test_definition_2_and_stopping_threshold(g1k, pi1k, k):
     s, eps = 0, 0.5
