@@ -132,6 +132,60 @@ def push(g, s: int, alpha: float, rmax: float, max_rounds: int = 100000,
     return out
 
 
+def push_replay(g, s: int, alpha: float, rmax: float, frontiers) -> dict:
+    """Algorithm 1 from r = e_s with the frontier of every synchronous round
+    given rather than tested. Algorithm 1 may push nodes in any order and
+    eqn:layerppr holds for every sequence of pushes, so replaying another
+    run's frontiers in FP64 rebuilds the state that run should have reached.
+    Each round pushes its listed nodes (ascending, as given) exactly as the
+    synchronous push does: x = r(v), r(v) = 0, q(v) += alpha x, then
+    r(u) += (1 - alpha) x / d(v) for u in N_out(v) in CSR order.
+
+    Before each round it measures how far the listed nodes are from the push
+    test r(v) > r_max d(v) and how far the unlisted ones are over it, both
+    relative to the threshold; after the last round, how far any node is
+    over it. Returns r and q (FP64), max_listed_shortfall (the largest
+    (r_max d(v) - r(v)) / (r_max d(v)) over listed nodes: negative when every
+    listed node passes the test) and max_unlisted_excess (the largest
+    (r(v) - r_max d(v)) / (r_max d(v)) over unlisted nodes and the final
+    state: at most 0 when no node was left over its threshold)."""
+    if not rmax > 0.0:
+        raise ValueError("rmax must be positive")
+    rp = np.asarray(g.rowptr, np.int64)
+    ci = np.asarray(g.colidx, np.int64)
+    n = rp.shape[0] - 1
+    deg = np.diff(rp)
+    thr = rmax * deg.astype(np.float64)
+    r = np.zeros(n, np.float64)
+    q = np.zeros(n, np.float64)
+    r[int(s)] = 1.0
+    shortfall = -math.inf
+    excess = -math.inf
+    for F in frontiers:
+        F = np.asarray(F, np.int64)
+        if F.size and (np.any(np.diff(F) <= 0) or F[0] < 0 or F[-1] >= n):
+            raise ValueError("a frontier must hold distinct node ids in ascending order")
+        listed = np.zeros(n, bool)
+        listed[F] = True
+        if F.size:
+            shortfall = max(shortfall, float(np.max((thr[F] - r[F]) / thr[F])))
+        if not listed.all():
+            rest = ~listed
+            excess = max(excess, float(np.max((r[rest] - thr[rest]) / thr[rest])))
+        x = r[F].copy()
+        r[F] = 0.0
+        q[F] += alpha * x
+        d = deg[F]
+        inc = ((1.0 - alpha) * x) / d.astype(np.float64)
+        # the out-edges of the listed nodes, node by node in CSR order
+        before = np.cumsum(d) - d
+        edges = np.repeat(rp[F] - before, d) + np.arange(int(d.sum()))
+        np.add.at(r, ci[edges], np.repeat(inc, d))
+    excess = max(excess, float(np.max((r - thr) / thr)))
+    return dict(r=r, q=q, rounds=len(frontiers), max_listed_shortfall=shortfall,
+                max_unlisted_excess=excess)
+
+
 def push_sweep(g, s: int, alpha: float, rmaxes, omega_unit: float,
                max_rounds: int = 100000) -> dict:
     """Algorithm 1 at r_max = rmaxes[0], then continued from the state it
