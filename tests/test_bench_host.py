@@ -58,3 +58,16 @@ def test_committed_traffic_records_are_well_formed(path):
     assert len(rec["source_sha256"]) == 64
     for src in rec["sources"]:
         assert os.path.exists(os.path.join(ROOT, src)), src
+
+
+@pytest.mark.parametrize("path", sorted(
+    p for p in os.listdir(os.path.join(ROOT, "profiles")) if p.endswith(".md")))
+def test_profile_summaries_name_commands_over_committed_files(path):
+    text = open(os.path.join(ROOT, "profiles", path)).read()
+    cmds = [line.strip() for line in text.splitlines() if line.strip().startswith("rocprofv3")]
+    assert cmds, "a summary gives the command that made it"
+    for cmd in cmds:
+        prog = cmd.split(" -- ", 1)[1].split()
+        assert prog[0] in ("python3", "python") and prog[1].endswith(".py"), cmd
+        assert os.path.exists(os.path.join(ROOT, prog[1])), cmd
+        assert not prog[1].startswith("_work"), cmd
