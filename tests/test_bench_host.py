@@ -64,7 +64,8 @@ def test_committed_traffic_records_are_well_formed(path):
     p for p in os.listdir(os.path.join(ROOT, "profiles")) if p.endswith(".md")))
 def test_profile_summaries_name_commands_over_committed_files(path):
     text = open(os.path.join(ROOT, "profiles", path)).read()
-    cmds = [line.strip() for line in text.splitlines() if line.strip().startswith("rocprofv3")]
+    cmds = [line.strip() for line in text.splitlines()
+            if line.strip().startswith("rocprofv3") and " -- " in line]
     assert cmds, "a summary gives the command that made it"
     for cmd in cmds:
         prog = cmd.split(" -- ", 1)[1].split()
