@@ -12,7 +12,8 @@ of eqn:rmax), the walks (weight, stop test, neighbour choice, keying, where
 the weight lands, the Philox key schedule), the top-k tie order, Algorithm 3
 (residue scaling, the alpha r start, the forced first move), Algorithm 5
 (eps / 2, the split of p_f, the stopping test, the delta sequence), the
-FORA+ index size, source distributions (estimate, walk key) and the MLP
+FORA+ index size, source distributions (estimate, walk key), the frontier
+replay (reserve update, final check) and the MLP
 reference (GELU derivative, loss gradient, Adam's bias correction, BF16
 ties, a feature)."""
 import os
@@ -97,6 +98,12 @@ MUTATIONS = {
         PY, 'wk = walks(g, DIST_KEY0, seed, c["t_alpha"], pv, po, pw)',
         'wk = walks(g, 0, seed, c["t_alpha"], pv, po, pw)',
         ["tests/test_dist_oracle.py::test_point_mass_is_the_single_source_query"]),
+    "replay_reserve_without_alpha": (
+        PY, "        q[F] += alpha * x\n", "        q[F] += x\n",
+        ["tests/test_replay_oracle.py::test_replay_of_own_frontiers_is_bit_exact"]),
+    "replay_without_final_check": (
+        PY, "    excess = max(excess, float(np.max((r - thr) / thr)))\n", "",
+        ["tests/test_replay_oracle.py::test_wrong_frontiers_are_reported"]),
     "mlp_gelu_grad_term": (MLP, "return _cdf(z) + z * _phi(z)", "return _cdf(z)",
                            [LO + "test_gelu_closed_forms",
                             LO + "test_backward_matches_finite_differences"]),

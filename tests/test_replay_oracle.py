@@ -52,6 +52,9 @@ def test_wrong_frontiers_are_reported(g1k):
     extra = np.sort(np.concatenate([fr[1], [idle]]))
     rep = oracle.push_replay(g1k, 0, ALPHA, rmax, [fr[0], extra] + fr[2:])
     assert rep["max_listed_shortfall"] == pytest.approx(1.0)
+    # the last round left out: its nodes end over their thresholds
+    rep = oracle.push_replay(g1k, 0, ALPHA, rmax, fr[:-1])
+    assert rep["max_unlisted_excess"] > 0
     with pytest.raises(ValueError):
         oracle.push_replay(g1k, 0, ALPHA, rmax, [fr[0], fr[1][::-1]] + fr[2:])
 
