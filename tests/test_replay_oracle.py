@@ -47,7 +47,7 @@ def test_wrong_frontiers_are_reported(g1k):
     # the source left out of round 0: it stays far over its threshold
     rep = oracle.push_replay(g1k, 0, ALPHA, rmax, [fr[0][:0]] + fr[1:])
     assert rep["max_unlisted_excess"] > 1.0
-    # a node with no residue listed in round 1: it is short by its whole threshold
+    # a node with no residue listed in the second push round: short by its whole threshold
     idle = int(np.setdiff1d(np.arange(g1k.n), fr[1])[0])
     extra = np.sort(np.concatenate([fr[1], [idle]]))
     rep = oracle.push_replay(g1k, 0, ALPHA, rmax, [fr[0], extra] + fr[2:])
