@@ -94,6 +94,8 @@ def autotune(G: fora.Graph, queries, path: str | None = None, force: bool = Fals
         if best_ratio is None or m["push"] < best_ratio[1]:
             best_ratio = (pr, m["push"])
     base["pull_ratio"] = best_ratio[0]
+    if log:
+        log(f"autotune: pull_ratio {best_ratio[0]} (push {best_ratio[1]:.2f} ms)")
     best_push = None
     for pb in PUSH_BLOCKS:
         G.set_tuning(**dict(base, push_blocks_per_cu=pb))
@@ -102,8 +104,12 @@ def autotune(G: fora.Graph, queries, path: str | None = None, force: bool = Fals
         if best_push is None or m["push"] < best_push[1]:
             best_push = (pb, m["push"], m["rounds"])
     base["push_blocks_per_cu"] = best_push[0]
+    if log:
+        log(f"autotune: push_blocks_per_cu {best_push[0]} (push {best_push[1]:.2f} ms)")
     best_walk = None
     for agg in WALK_AGG:
+        if log:
+            log(f"autotune: walk shapes with walk_agg={agg}")
         for wb in WALK_BLOCKS:
             for ch in WALK_CHUNKS:
                 G.set_tuning(**dict(base, walk_blocks_per_cu=wb, walk_chunk=ch, walk_agg=agg))

@@ -304,7 +304,8 @@ def workload(name: str) -> tuple[Graph, np.ndarray]:
         train = sources_uniform(g, 4096, seed=2021, exclude=bench)
         return g, np.concatenate([train, bench])
     if name == "rmat23":
-        g = rmat_graph(23, seed=23)
+        # the multithreaded sampler builds this graph in seconds (numpy: a minute)
+        g = rmat_graph(23, seed=23, sampler="c")
         return g, sources_by_degree(g, 1024, seed=2323)
     if name == "rmat22":
         g = rmat_graph(22, seed=22)
