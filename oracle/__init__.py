@@ -61,6 +61,8 @@ def _load():
     lib.oracle_push_balanced.argtypes = [i32, P, P, i32, f64, f64, f64, f64, P, P, i32, P, P,
                                          P, i64, P, P, P]
     lib.oracle_push_balanced.restype = i32
+    lib.oracle_push_replay.argtypes = [i32, P, P, f64, f64, P, P, i32, P, P, P]
+    lib.oracle_push_replay.restype = i32
     lib.oracle_topk.argtypes = [i32, P, i32, P, P]
     lib.oracle_topk.restype = ctypes.c_int
     _lib = lib
@@ -132,14 +134,13 @@ def push(g, s: int, alpha: float, rmax: float, max_rounds: int = 100000,
     return out
 
 
-def push_replay(g, s: int, alpha: float, rmax: float, frontiers) -> dict:
-    """Algorithm 1 from r = e_s with the frontier of every synchronous round
-    given rather than tested. Algorithm 1 may push nodes in any order and
-    eqn:layerppr holds for every sequence of pushes, so replaying another
-    run's frontiers in FP64 rebuilds the state that run should have reached.
-    Each round pushes its listed nodes (ascending, as given) exactly as the
-    synchronous push does: x = r(v), r(v) = 0, q(v) += alpha x, then
-    r(u) += (1 - alpha) x / d(v) for u in N_out(v) in CSR order.
+def push_replay(g, s: int, alpha: float, rmax: float, frontiers, r0=None) -> dict:
+    """Algorithm 1 with the frontier of every synchronous round given rather
+    than tested, from r = e_s (or r = r0, a source distribution), q = 0.
+    Algorithm 1 may push nodes in any order and eqn:layerppr holds for every
+    sequence of pushes, so replaying another run's frontiers in FP64 rebuilds
+    the state that run should have reached. Each round pushes its listed
+    nodes (ascending) exactly as the oracle's synchronous push does.
 
     Before each round it measures how far the listed nodes are from the push
     test r(v) > r_max d(v) and how far the unlisted ones are over it, both
@@ -151,39 +152,28 @@ def push_replay(g, s: int, alpha: float, rmax: float, frontiers) -> dict:
     state: at most 0 when no node was left over its threshold)."""
     if not rmax > 0.0:
         raise ValueError("rmax must be positive")
-    rp = np.asarray(g.rowptr, np.int64)
-    ci = np.asarray(g.colidx, np.int64)
+    lib = _load()
+    rp, ci = _csr(g)
     n = rp.shape[0] - 1
-    deg = np.diff(rp)
-    thr = rmax * deg.astype(np.float64)
-    r = np.zeros(n, np.float64)
+    if r0 is None:
+        r = np.zeros(n, np.float64)
+        r[int(s)] = 1.0
+    else:
+        r = np.array(r0, np.float64, copy=True).reshape(n)
     q = np.zeros(n, np.float64)
-    r[int(s)] = 1.0
-    shortfall = -math.inf
-    excess = -math.inf
-    for F in frontiers:
-        F = np.asarray(F, np.int64)
-        if F.size and (np.any(np.diff(F) <= 0) or F[0] < 0 or F[-1] >= n):
-            raise ValueError("a frontier must hold distinct node ids in ascending order")
-        listed = np.zeros(n, bool)
-        listed[F] = True
-        if F.size:
-            shortfall = max(shortfall, float(np.max((thr[F] - r[F]) / thr[F])))
-        if not listed.all():
-            rest = ~listed
-            excess = max(excess, float(np.max((r[rest] - thr[rest]) / thr[rest])))
-        x = r[F].copy()
-        r[F] = 0.0
-        q[F] += alpha * x
-        d = deg[F]
-        inc = ((1.0 - alpha) * x) / d.astype(np.float64)
-        # the out-edges of the listed nodes, node by node in CSR order
-        before = np.cumsum(d) - d
-        edges = np.repeat(rp[F] - before, d) + np.arange(int(d.sum()))
-        np.add.at(r, ci[edges], np.repeat(inc, d))
-    excess = max(excess, float(np.max((r - thr) / thr)))
-    return dict(r=r, q=q, rounds=len(frontiers), max_listed_shortfall=shortfall,
-                max_unlisted_excess=excess)
+    frontiers = [np.asarray(F, np.int32).reshape(-1) for F in frontiers]
+    sizes = np.array([F.size for F in frontiers], np.int64)
+    flat = np.ascontiguousarray(np.concatenate(frontiers) if frontiers else
+                                np.zeros(0, np.int32), np.int32)
+    out = np.zeros(2, np.float64)
+    rc = lib.oracle_push_replay(n, _p(rp), _p(ci), alpha, rmax, _p(r), _p(q), len(frontiers),
+                                _p(sizes), _p(flat), _p(out))
+    if rc == -1:
+        raise ValueError("a frontier must hold distinct node ids in ascending order")
+    if rc != 0:
+        raise RuntimeError(f"oracle_push_replay failed ({rc})")
+    return dict(r=r, q=q, rounds=len(frontiers), max_listed_shortfall=float(out[0]),
+                max_unlisted_excess=float(out[1]))
 
 
 def push_sweep(g, s: int, alpha: float, rmaxes, omega_unit: float,

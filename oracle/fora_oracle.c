@@ -113,6 +113,30 @@ void oracle_constants(int64_t m, double alpha, double eps, double delta,
   out[4] = floor(alpha * 4294967296.0);
 }
 
+/* One synchronous round over the frontier front[0 .. nf-1] (ascending):    */
+/* every listed residue is read and cleared before any increment lands,      */
+/* then the increments are applied node by node in CSR order. x is scratch   */
+/* of nf doubles. Returns the residue mass pushed (sum of x).                */
+static double push_round(const int32_t *rowptr, const int32_t *colidx, double alpha,
+                         const int32_t *front, int32_t nf, double *r, double *q,
+                         double *x) {
+  double pushed = 0.0;
+  for (int32_t i = 0; i < nf; ++i) {
+    int32_t v = front[i];
+    x[i] = r[v];
+    r[v] = 0.0;
+    q[v] += alpha * x[i];
+    pushed += x[i];
+  }
+  for (int32_t i = 0; i < nf; ++i) {
+    int32_t v = front[i];
+    int32_t d = rowptr[v + 1] - rowptr[v];
+    double inc = ((1.0 - alpha) * x[i]) / (double)d;
+    for (int32_t e = rowptr[v]; e < rowptr[v + 1]; ++e) r[colidx[e]] += inc;
+  }
+  return pushed;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Forward Push (Algorithm 1) in synchronous rounds.                         */
 /* Round t: F = { v ascending : r(v) > r_max * d(v) }; stop when F is empty. */
@@ -180,20 +204,8 @@ static int32_t push_core(int32_t n, const int32_t *rowptr, const int32_t *colidx
       memcpy(frontier_log + logged, front, sizeof(int32_t) * (size_t)nf);
       logged += nf;
     }
-    for (int32_t i = 0; i < nf; ++i) {
-      int32_t v = front[i];
-      x[i] = r[v];
-      r[v] = 0.0;
-      q[v] += alpha * x[i];
-      pushed += x[i];
-    }
-    for (int32_t i = 0; i < nf; ++i) {
-      int32_t v = front[i];
-      int32_t d = rowptr[v + 1] - rowptr[v];
-      double inc = ((1.0 - alpha) * x[i]) / (double)d;
-      for (int32_t e = rowptr[v]; e < rowptr[v + 1]; ++e) r[colidx[e]] += inc;
-      ops += d;
-    }
+    pushed += push_round(rowptr, colidx, alpha, front, nf, r, q, x);
+    for (int32_t i = 0; i < nf; ++i) ops += rowptr[front[i] + 1] - rowptr[front[i]];
     ++rounds;
   }
   if (edge_ops) *edge_ops = ops;
@@ -241,6 +253,67 @@ int32_t oracle_push(int32_t n, const int32_t *rowptr, const int32_t *colidx,
   return oracle_push_continue(n, rowptr, colidx, alpha, rmax, r, q, max_rounds,
                               round_sizes, edge_ops, frontier_log,
                               frontier_cap, min_margin);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Frontier replay: Algorithm 1 from the caller's (r, q) with the frontier   */
+/* of every synchronous round given rather than tested. Algorithm 1 may push */
+/* nodes in any order and eqn:layerppr holds for every sequence of pushes,   */
+/* so replaying another run's frontiers in FP64 rebuilds the state that run  */
+/* should have reached. Each round is push_round, as in the oracle's own     */
+/* push. Before each round it measures how far the listed nodes are from the */
+/* push test r(v) > r_max d(v) and how far the unlisted ones are over it,    */
+/* both relative to the threshold; after the last round, how far any node is */
+/* over it. out[0] = max listed shortfall (r_max d(v) - r(v)) / (r_max d(v)) */
+/* (negative when every listed node passes), out[1] = max unlisted excess    */
+/* (r(v) - r_max d(v)) / (r_max d(v)) over every round and the final state   */
+/* (at most 0 when no node was left over its threshold); both start at       */
+/* -infinity. frontiers holds the rounds back to back, round_sizes[t]        */
+/* entries each. Returns 0, -1 if a frontier is not strictly ascending in    */
+/* [0, n), -3 if out of memory.                                              */
+/* ------------------------------------------------------------------------ */
+int32_t oracle_push_replay(int32_t n, const int32_t *rowptr, const int32_t *colidx,
+                           double alpha, double rmax, double *r, double *q,
+                           int32_t rounds, const int64_t *round_sizes,
+                           const int32_t *frontiers, double out[2]) {
+  char *listed = (char *)calloc((size_t)n, 1);
+  double *x = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!listed || !x) { free(listed); free(x); return -3; }
+  double shortfall = -INFINITY, excess = -INFINITY;
+  int64_t off = 0;
+  int32_t rc = 0;
+  for (int32_t t = 0; t < rounds && rc == 0; ++t) {
+    const int32_t *F = frontiers + off;
+    const int64_t nf = round_sizes[t];
+    for (int64_t i = 0; i < nf; ++i) {
+      if (F[i] < 0 || F[i] >= n || (i > 0 && F[i] <= F[i - 1])) { rc = -1; break; }
+      listed[F[i]] = 1;
+    }
+    if (rc != 0) break;
+    for (int32_t v = 0; v < n; ++v) {
+      const int32_t deg = rowptr[v + 1] - rowptr[v];
+      const double thr = rmax * (double)deg;
+      double rel = listed[v] ? (thr - r[v]) / thr : (r[v] - thr) / thr;
+      if (listed[v]) { if (rel > shortfall) shortfall = rel; }
+      else if (rel > excess) excess = rel;
+    }
+    push_round(rowptr, colidx, alpha, F, (int32_t)nf, r, q, x);
+    for (int64_t i = 0; i < nf; ++i) listed[F[i]] = 0;
+    off += nf;
+  }
+  if (rc == 0) {
+    for (int32_t v = 0; v < n; ++v) {
+      const int32_t deg = rowptr[v + 1] - rowptr[v];
+      const double thr = rmax * (double)deg;
+      double rel = (r[v] - thr) / thr;
+      if (rel > excess) excess = rel;
+    }
+  }
+  out[0] = shortfall;
+  out[1] = excess;
+  free(listed);
+  free(x);
+  return rc;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -13,7 +13,7 @@ the weight lands, the Philox key schedule), the top-k tie order, Algorithm 3
 (residue scaling, the alpha r start, the forced first move), Algorithm 5
 (eps / 2, the split of p_f, the stopping test, the delta sequence), the
 FORA+ index size, source distributions (estimate, walk key), the frontier
-replay (reserve update, final check) and the MLP
+replay (its push test, final check; its rounds share the push's code) and the MLP
 reference (GELU derivative, loss gradient, Adam's bias correction, BF16
 ties, a feature)."""
 import os
@@ -98,11 +98,12 @@ MUTATIONS = {
         PY, 'wk = walks(g, DIST_KEY0, seed, c["t_alpha"], pv, po, pw)',
         'wk = walks(g, 0, seed, c["t_alpha"], pv, po, pw)',
         ["tests/test_dist_oracle.py::test_point_mass_is_the_single_source_query"]),
-    "replay_reserve_without_alpha": (
-        PY, "        q[F] += alpha * x\n", "        q[F] += x\n",
+    "replay_listed_test_inverted": (
+        C, "double rel = listed[v] ? (thr - r[v]) / thr : (r[v] - thr) / thr;",
+        "double rel = listed[v] ? (r[v] - thr) / thr : (thr - r[v]) / thr;",
         ["tests/test_replay_oracle.py::test_replay_of_own_frontiers_is_bit_exact"]),
     "replay_without_final_check": (
-        PY, "    excess = max(excess, float(np.max((r - thr) / thr)))\n", "",
+        C, "double rel = (r[v] - thr) / thr;\n      if (rel > excess) excess = rel;", "",
         ["tests/test_replay_oracle.py::test_wrong_frontiers_are_reported"]),
     "mlp_gelu_grad_term": (MLP, "return _cdf(z) + z * _phi(z)", "return _cdf(z)",
                            [LO + "test_gelu_closed_forms",
