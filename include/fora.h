@@ -59,7 +59,8 @@ typedef struct fora_stats {
   int64_t plan_entries;    /* nodes with r(v) > 0 (walk plan length)           */
   uint64_t walks;          /* W = sum over v of omega_v                        */
   uint64_t steps;          /* walk moves (edge traversals) over all walks      */
-  double r_sum;            /* sum of residues after the push (FP64 sum)        */
+  double r_sum;            /* sum of residues after the push (the exact sum of
+                              the fixed-point residues, rounded to FP64)       */
   double rmax;             /* r_max used                                       */
   double omega_unit;       /* (2 eps/3 + 2) ln(2/p_f) / (eps^2 delta)          */
   uint32_t t_alpha;        /* floor(alpha * 2^32)                              */
@@ -91,7 +92,7 @@ typedef struct fora_query {
 /* Algorithm 3 (section 5), per query:
  * FORA_PRUNE_ZERO_HOP (section 5.1): pi_hat starts at q + alpha r; from each
  *   v with residue, omega_v = ceil(r'(v) omega_unit) walks with
- *   r' = (1 - alpha) r (FP64 from the FP32 residue), each starting with a
+ *   r' = (1 - alpha) r (FP64 from the fixed-point residue), each starting with a
  *   forced move (the step-0 Philox block only picks the out-neighbour) and
  *   adding r'(v) / omega_v at its end point.
  * FORA_BALANCE (section 5.2): before each push round the push stops once its
@@ -119,7 +120,8 @@ typedef struct fora_query {
 /* Dense per-query arrays inside a workspace, for inspection. Query b's row
  * starts at b*n. Valid after a call on that workspace has completed. */
 typedef struct fora_views {
-  float *residue;             /* r(s, v), FP32 [batch][n]                     */
+  uint64_t *residue_fx;       /* r(s, v), unsigned fixed point with 62
+                                 fraction bits [batch][n]                     */
   float *reserve;             /* q(s, v), FP32 [batch][n]                     */
   uint64_t *walk_count;       /* walks ending at v, [batch][n]; zero unless
                                  the query set FORA_WALK_COUNTS            */
@@ -210,7 +212,10 @@ int fora_ssppr(const fora_graph *g, int32_t src, double alpha, double eps,
  * rounds, walk plans, walks and selections run in shared kernels. Query b's
  * result is written to d_ids[b*kmax ...], d_vals[b*kmax ...]; kmax must be at
  * least every query's k. Each query's result equals what fora_ssppr returns
- * for it (walk end points bit-identical given identical residues). h_stats
+ * for it, bit for bit: residues are summed in fixed point, walks are keyed by
+ * (source, seed, start node, walk index, step), and end-point weights are
+ * summed as integers, so no result depends on the batch or on the order in
+ * which the device runs the work. h_stats
  * (nullable) is an array of `batch` entries.
  * With tuning.graph_rounds = R > 0 the whole sequence (zero fill, init, R
  * push rounds, plan, walks, top-k) is captured once per (batch, kmax,
@@ -229,13 +234,13 @@ int fora_ssppr_batch(const fora_graph *g, int32_t batch,
  * pi(sigma, t) = q(t) + sum_v r(v) pi(v, t), so walks, estimate and top-k are
  * those of fora_ssppr_batch and the eps guarantee holds for pi(sigma, .).
  * d_sigma: double[batch][n], device, caller-owned, read once; each row a
- * probability distribution (entries rounded to the FP32 residues; FORA_BALANCE
- * assumes a row sums to 1). The queries' src fields are not used; walks are
- * keyed by (0xFFFFFFFF, seed) (the index key with FORA_USE_INDEX). Same
- * workspace, outputs and flags as fora_ssppr_batch; never replayed from a
- * captured graph (graph_rounds is ignored). Errors: those of
- * fora_ssppr_batch; FORA_E_ARG for a null d_sigma or an entry that is
- * negative or not finite (reported when the call completes). */
+ * probability distribution (entries rounded to the fixed-point residues;
+ * FORA_BALANCE assumes a row sums to 1). The queries' src fields are not
+ * used; walks are keyed by (0xFFFFFFFF, seed) (the index key with
+ * FORA_USE_INDEX). Same workspace, outputs and flags as fora_ssppr_batch;
+ * never replayed from a captured graph (graph_rounds is ignored). Errors:
+ * those of fora_ssppr_batch; FORA_E_ARG for a null d_sigma or an entry
+ * outside [0, 1] or not a number (reported when the call completes). */
 int fora_dist_batch(const fora_graph *g, int32_t batch, const fora_query *h_queries,
                     const double *d_sigma, int32_t kmax, void *d_ws, size_t ws_bytes,
                     int32_t *d_ids, float *d_vals, fora_stats *h_stats, void *stream);

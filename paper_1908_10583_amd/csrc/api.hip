@@ -147,7 +147,7 @@ QueryDev plan_query(const fora_graph* g, const fora_query& q, bool dist = false)
 
 int error_code_from_flags(int flags) {
   if (flags & kErrBadDist)
-    return fail(FORA_E_ARG, "source distribution entries must be finite and non-negative");
+    return fail(FORA_E_ARG, "source distribution entries must lie in [0, 1]");
   if (flags & kErrBadPlan)
     return fail(FORA_E_ARG, "walk plan nodes must be strictly increasing ids in [0, n)");
   if (flags & kErrOmegaOverflow)
@@ -269,6 +269,7 @@ int finish(fora_graph* g, const Call& c, int batch, hipStream_t s, fora_stats* h
     for (int b = 0; b < batch; ++b) {
       fora_stats& o = h_stats[b];
       std::memset(&o, 0, sizeof(o));
+      u64 r_sum_fx = 0;
       for (int k = 0; k < kStatSlots; ++k) {
         const StatSlot& q = slots[(size_t)b * kStatSlots + k];
         o.rounds = std::max(o.rounds, q.rounds);
@@ -278,10 +279,11 @@ int finish(fora_graph* g, const Call& c, int batch, hipStream_t s, fora_stats* h
         o.plan_entries += (int64_t)q.entries;
         o.walks += q.walks;
         o.steps += q.steps;
-        o.r_sum += q.r_sum;
+        r_sum_fx += q.r_sum_fx;
         o.pull_rounds += (uint32_t)q.pull_rounds;
         o.balance_stopped |= (uint32_t)(q.balance_stopped != 0);
       }
+      o.r_sum = std::ldexp((double)r_sum_fx, -62);
       o.rmax = qd[b].rmax;
       o.omega_unit = qd[b].omega_unit;
       o.t_alpha = qd[b].t_alpha;
@@ -454,14 +456,14 @@ Layout make_layout(const GraphDev& g, int32_t batch) {
   L.ctrl = take(sizeof(Ctrl));
   L.zero_begin = L.ctrl;
   L.qstats = take(sizeof(StatSlot) * (size_t)kStatSlots * batch);
-  L.r = take(4 * cap);
+  L.r = take(8 * cap);
   L.q = take(4 * cap);
   L.cnt = take(8 * cap);
   L.acc = take(8 * cap);
   L.hist = take(4 * (size_t)kHistBins * batch);
   L.cand_cnt = take(4 * (size_t)batch);
   const size_t pg = (size_t)pull_group_for(batch);
-  L.incd = take(4 * (((size_t)batch + pg - 1) / pg * pg) * (size_t)n);  // whole pull groups
+  L.incd = take(8 * (((size_t)batch + pg - 1) / pg * pg) * (size_t)n);  // whole pull groups
   L.ecnt = take(8 * 2 * (size_t)kStatSlots * batch);
   L.stop = take(4 * (size_t)batch);
   L.zero_end = align_up(off, 256);
@@ -472,7 +474,7 @@ Layout make_layout(const GraphDev& g, int32_t batch) {
   L.pi = take(4 * cap);
   L.fr0 = take(8 * cap);
   L.fr1 = take(8 * cap);
-  L.frx = take(4 * cap);
+  L.frx = take(8 * cap);
   L.hub_idx = take(8 * (size_t)L.hub_cap);
   L.hub_base = take(8 * (size_t)L.hub_cap);
   L.plan_gi = take(8 * cap);
@@ -496,17 +498,17 @@ Ws carve(const Layout& L, void* base) {
   w.ctrl = (Ctrl*)(p + L.ctrl);
   w.qstats = (QueryStatsDev*)(p + L.qstats);
   w.queries = (QueryDev*)(p + L.queries);
-  w.r = (float*)(p + L.r);
+  w.r = (u64*)(p + L.r);
   w.q = (float*)(p + L.q);
   w.cnt = (u64*)(p + L.cnt);
   w.acc = (u64*)(p + L.acc);
   w.pi = (float*)(p + L.pi);
   w.fr[0] = (u64*)(p + L.fr0);
   w.fr[1] = (u64*)(p + L.fr1);
-  w.frx = (float*)(p + L.frx);
+  w.frx = (u64*)(p + L.frx);
   w.hub_idx = (u64*)(p + L.hub_idx);
   w.hub_base = (u64*)(p + L.hub_base);
-  w.incd = (float*)(p + L.incd);
+  w.incd = (u64*)(p + L.incd);
   w.ecnt = (u64*)(p + L.ecnt);
   w.mode = (int32_t*)(p + L.mode);
   w.pull_list = (int32_t*)(p + L.pull_list);
@@ -836,7 +838,7 @@ int fora_workspace_views(const fora_graph* g, int32_t batch, void* d_ws, fora_vi
   if (batch < 1 || batch > FORA_MAX_BATCH) return fail(FORA_E_ARG, "batch out of range");
   const Layout L = make_layout(g->dev, batch);
   const Ws w = carve(L, d_ws);
-  v->residue = w.r;
+  v->residue_fx = (uint64_t*)w.r;
   v->reserve = w.q;
   v->walk_count = (uint64_t*)w.cnt;
   v->walk_weight_fx = (uint64_t*)w.acc;

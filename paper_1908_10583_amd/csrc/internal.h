@@ -4,12 +4,13 @@
 //   ctrl      one Ctrl block: frontier counters, walk work queue, error flags
 //   qstats    QueryStats[batch]: per-query counters (device side)
 //   queries   QueryDev[batch]: per-query constants computed on the host
-//   r, q      float[batch][n]   residue / reserve (FP32)
+//   r         uint64[batch][n]  residue, unsigned fixed point (62 fraction bits)
+//   q         float[batch][n]   reserve (FP32)
 //   cnt       uint64[batch][n]  walk end-point counts
 //   acc       uint64[batch][n]  walk weights, fixed point (62 fraction bits)
 //   pi        float[batch][n]   q + acc, the estimate
 //   fr0/fr1   uint64[batch*n]   frontier entries (query << 32 | node)
-//   frx       float[batch*n]    per-frontier-entry increment (1-alpha) x / d
+//   frx       uint64[batch*n]   per-frontier-entry increment (1-alpha) x / d (fixed point)
 //   plan_*    walk plan: entry (query << 32 | node), walk offset, weight
 //   tiles     per-tile counts and offsets for the plan scan
 //   topk      histograms, selection state and candidates
@@ -39,6 +40,25 @@ constexpr int kHubDeg = 2048;          // frontier entries above this are split 
 constexpr int kHubPiece = 2048;        // edges per piece of a split entry
 constexpr int kPullRatio = 16;         // default: pull a round if frontier edges * this > n + m
 constexpr double kFx = 4611686018427387904.0;  // 2^62
+constexpr unsigned long long kFxOne = 1ull << 62;  // 1.0 in the fixed point of residues
+
+// Residues are unsigned fixed point with 62 fraction bits. Increments are
+// rounded once, when they are formed (one FP64 value per pushed node), and
+// then summed as integers, so every sum is exact and independent of the order
+// in which the atomics land: a query pushes the same nodes in the same rounds
+// whatever else runs beside it, and one run equals the next bit for bit.
+__device__ __forceinline__ double fx_to_double(unsigned long long x) {
+  return (double)x * (1.0 / kFx);
+}
+__device__ __forceinline__ unsigned long long fx_from_double(double x) {
+  return __double2ull_rn(x * kFx);
+}
+// The push test r(v) > r_max d(v), with r_max d(v) the FP64 product: for an
+// integer residue r_fx it holds iff r_fx > floor(r_max d(v) 2^62).
+__device__ __forceinline__ unsigned long long fx_threshold(double rmax, int d) {
+  const double t = (rmax * (double)d) * kFx;
+  return t < 18446744073709551616.0 ? (unsigned long long)t : ~0ull;
+}
 
 // Error flags raised by kernels.
 enum : int {
@@ -73,11 +93,11 @@ struct StatSlot {
   u64 entries;
   u64 walks;
   u64 steps;
-  double r_sum;
+  u64 r_sum_fx;          // sum of the fixed-point residues after the push
   int32_t rounds;
   int32_t term_violations;
   u64 pull_rounds;
-  double mass;           // residue pushed (sum of x), FORA_BALANCE queries only
+  u64 mass_fx;           // residue pushed (sum of x, fixed point), FORA_BALANCE only
   u64 balance_stopped;   // set in slot 0 by the round-boundary test
 };
 typedef StatSlot QueryStatsDev;
@@ -157,16 +177,16 @@ struct Ws {
   Ctrl* ctrl;
   QueryStatsDev* qstats;
   QueryDev* queries;
-  float* r;
+  u64* r;  // fixed point, kFxOne = 1
   float* q;
   u64* cnt;
   u64* acc;
   float* pi;
   u64* fr[2];
-  float* frx;
+  u64* frx;       // per-entry increment, fixed point
   u64* hub_idx;   // frontier index of each split entry
   u64* hub_base;  // first piece number of each split entry
-  float* incd;    // [ceil(batch / G)][n][G]: frontier increments by degree rank, G =
+  u64* incd;      // [ceil(batch / G)][n][G]: frontier increments by degree rank, G =
                   // pull_group_for(batch) queries per node unit, dense, for pull rounds
   u64* ecnt;      // [2][batch][kStatSlots]: frontier edges per query, by round parity
   int32_t* mode;  // [batch]: 1 if the query's current round pulls

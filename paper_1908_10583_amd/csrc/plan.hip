@@ -1,11 +1,12 @@
 // Walk plan (Algorithm 2, the loop over nodes with residue): for every
 // (query b, node v) with r(v) > 0,
-//   omega_v = ceil(r(v) * omega_unit)          (FP64 from the FP32 residue)
+//   omega_v = ceil(r(v) * omega_unit)          (FP64 from the fixed-point residue)
 //   weight  = round(r(v) / omega_v * 2^62)     (unsigned fixed point)
 // and an exclusive scan of omega_v over (b, v) in row-major order gives every
 // walk a global id. With FORA_PRUNE_ZERO_HOP (Algorithm 3) the walks carry
-// r'(v) = (1 - alpha) r(v) instead (FP64 from the FP32 residue). Also collects r_sum per query and counts residues left
-// above r_max * d(v) (must be zero after the push).
+// r'(v) = (1 - alpha) r(v) instead. Also collects r_sum per query (an exact
+// integer sum of the fixed-point residues) and counts residues left above
+// r_max * d(v) (must be zero after the push).
 #include "internal.h"
 #include "scan.h"
 
@@ -17,45 +18,44 @@ constexpr int kScanThreads = 1024;
 
 // Tile pass 1: entries and walks per tile, per-query totals.
 __global__ __launch_bounds__(kPlanThreads) void k_plan_count(
-    const float* __restrict__ r, const QueryDev* __restrict__ Q, QueryStatsDev* QS,
+    const u64* __restrict__ r, const QueryDev* __restrict__ Q, QueryStatsDev* QS,
     const int2* __restrict__ info, int n, int tiles_per_row, uint32_t* tile_cnt,
     u64* tile_walks, Ctrl* ctrl) {
-  __shared__ float s_r[kPlanTile];
+  __shared__ u64 s_r[kPlanTile];
   __shared__ u64 s_tmp[kPlanThreads / 64];
-  __shared__ double s_tmpd[kPlanThreads / 64];
   if (ctrl->skip) return;  // uniform: the push has not finished (graph replay)
   const int b = blockIdx.y;
   const int v0 = blockIdx.x * kPlanTile;
-  const float* row = r + (size_t)b * n;
+  const u64* row = r + (size_t)b * n;
   for (int k = threadIdx.x; k < kPlanTile; k += kPlanThreads) {
     const int v = v0 + k;
-    s_r[k] = v < n ? row[v] : 0.0f;
+    s_r[k] = v < n ? row[v] : 0ull;
   }
   __syncthreads();
   const double wu = Q[b].omega_unit;
   const double rmax = Q[b].rmax;
   const double scale = (Q[b].flags & FORA_PRUNE_ZERO_HOP) ? 1.0 - Q[b].alpha : 1.0;
-  u64 c = 0, walks = 0, viol = 0;
-  double rs = 0.0;
+  u64 c = 0, walks = 0, viol = 0, rs = 0;
   bool ovf = false;
 #pragma unroll
   for (int k = 0; k < kPlanPerThread; ++k) {
     const int lv = threadIdx.x * kPlanPerThread + k;
-    const float rv = s_r[lv];
-    if (rv > 0.0f) {
-      const double om = ceil((scale == 1.0 ? (double)rv : scale * (double)rv) * wu);
+    const u64 rfx = s_r[lv];
+    if (rfx != 0ull) {
+      const double rv = fx_to_double(rfx);
+      const double om = ceil((scale == 1.0 ? rv : scale * rv) * wu);
       ovf |= om >= 4294967296.0;
       ++c;
       walks += (u64)om;
-      rs += (double)rv;
-      if ((double)rv > rmax * (double)info[v0 + lv].y) ++viol;
+      rs += rfx;
+      if (rfx > fx_threshold(rmax, info[v0 + lv].y)) ++viol;
     }
   }
   if (ovf) atomicOr(&ctrl->error, kErrOmegaOverflow);
   const u64 tc = block_sum(c, s_tmp);
   const u64 tw = block_sum(walks, s_tmp);
   const u64 tv = block_sum(viol, s_tmp);
-  const double trs = block_sum(rs, s_tmpd);
+  const u64 trs = block_sum(rs, s_tmp);
   if (threadIdx.x == 0) {
     const size_t tile = (size_t)b * tiles_per_row + blockIdx.x;
     tile_cnt[tile] = (uint32_t)tc;
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_count(
     if (tc) {
       atomicAdd(&st->entries, tc);
       atomicAdd(&st->walks, tw);
-      unsafeAtomicAdd(&st->r_sum, trs);
+      atomicAdd(&st->r_sum_fx, trs);
     }
     if (tv) atomicAdd(&st->term_violations, (int)tv);
   }
@@ -107,18 +107,18 @@ __global__ __launch_bounds__(kScanThreads) void k_plan_scan(
 
 // Tile pass 2: write the plan entries in (query, node) order.
 __global__ __launch_bounds__(kPlanThreads) void k_plan_write(
-    const float* __restrict__ r, const QueryDev* __restrict__ Q, int n, int tiles_per_row,
+    const u64* __restrict__ r, const QueryDev* __restrict__ Q, int n, int tiles_per_row,
     const u64* tile_eoff, const u64* tile_woff, u64* plan_gi, u64* plan_off, u64* plan_wfx,
     const Ctrl* ctrl) {
-  __shared__ float s_r[kPlanTile];
+  __shared__ u64 s_r[kPlanTile];
   __shared__ u64 s_tmp[kPlanThreads / 64];
   if (ctrl->skip) return;
   const int b = blockIdx.y;
   const int v0 = blockIdx.x * kPlanTile;
-  const float* row = r + (size_t)b * n;
+  const u64* row = r + (size_t)b * n;
   for (int k = threadIdx.x; k < kPlanTile; k += kPlanThreads) {
     const int v = v0 + k;
-    s_r[k] = v < n ? row[v] : 0.0f;
+    s_r[k] = v < n ? row[v] : 0ull;
   }
   __syncthreads();
   const size_t tile = (size_t)b * tiles_per_row + blockIdx.x;
@@ -128,9 +128,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_write(
   double om[kPlanPerThread];
 #pragma unroll
   for (int k = 0; k < kPlanPerThread; ++k) {
-    const float rv = s_r[threadIdx.x * kPlanPerThread + k];
-    om[k] = rv > 0.0f ? ceil((scale == 1.0 ? (double)rv : scale * (double)rv) * wu) : 0.0;
-    c += rv > 0.0f ? 1 : 0;
+    const double rv = fx_to_double(s_r[threadIdx.x * kPlanPerThread + k]);
+    om[k] = rv > 0.0 ? ceil((scale == 1.0 ? rv : scale * rv) * wu) : 0.0;
+    c += rv > 0.0 ? 1 : 0;
     walks += (u64)om[k];
   }
   u64 tc, tw;
@@ -139,11 +139,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_write(
 #pragma unroll
   for (int k = 0; k < kPlanPerThread; ++k) {
     const int lv = threadIdx.x * kPlanPerThread + k;
-    const float rv = s_r[lv];
-    if (rv > 0.0f) {
+    const double rv = fx_to_double(s_r[lv]);
+    if (rv > 0.0) {
       plan_gi[e] = ((u64)b << 32) | (uint32_t)(v0 + lv);
       plan_off[e] = woff;
-      const double rw = scale == 1.0 ? (double)rv : scale * (double)rv;
+      const double rw = scale == 1.0 ? rv : scale * rv;
       plan_wfx[e] = __double2ull_rn((rw / om[k]) * kFx);
       ++e;
       woff += (u64)om[k];
@@ -178,19 +178,19 @@ hipError_t launch_push_gate(const Ws& w, int rounds, hipStream_t s) {
 
 // W per query for the current residues (no plan written): sum over v of
 // ceil(r(v) * omega_unit).
-__global__ __launch_bounds__(kPlanThreads) void k_count_walks(const float* __restrict__ r,
+__global__ __launch_bounds__(kPlanThreads) void k_count_walks(const u64* __restrict__ r,
                                                               const QueryDev* __restrict__ Q,
                                                               int n, u64* walks) {
   __shared__ u64 s_tmp[kPlanThreads / 64];
   const int b = blockIdx.y;
   const double wu = Q[b].omega_unit;
-  const float* row = r + (size_t)b * n;
+  const u64* row = r + (size_t)b * n;
   u64 acc = 0;
   for (int k = threadIdx.x; k < kPlanTile; k += kPlanThreads) {
     const int v = blockIdx.x * kPlanTile + k;
     if (v < n) {
-      const float rv = row[v];
-      if (rv > 0.0f) acc += (u64)ceil((double)rv * wu);
+      const u64 rfx = row[v];
+      if (rfx != 0ull) acc += (u64)ceil(fx_to_double(rfx) * wu);
     }
   }
   const u64 t = block_sum(acc, s_tmp);

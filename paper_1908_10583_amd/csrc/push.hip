@@ -6,12 +6,17 @@
 //   then r(u) += sum of inc_v over v in F_t with u in N_out(v), and every u
 //   whose residue now exceeds r_max * d(u) joins F_{t+1}.
 // The snapshot is its own launch, so every frontier residue is read before
-// any increment of the same round lands. The residue test is made in FP64
-// on the FP32 residue (never a division).
+// any increment of the same round lands. Residues are unsigned fixed point
+// with 62 fraction bits: inc_v is formed once in FP64 and rounded to it, and
+// the sums are integer additions, so the result does not depend on the order
+// in which increments land (nor on the batch a query runs in). The push test
+// compares the integer residue with floor(r_max d(v) 2^62), which is the
+// exact test against the FP64 threshold (never a division).
 //
 // The increments are applied in one of two ways, chosen per query and round:
-// * push (sparse rounds): each frontier edge does a memory-side float atomic
-//   on r(u); the increment that lifts r(u) over its threshold enqueues u.
+// * push (sparse rounds): each frontier edge does a memory-side 64-bit
+//   integer atomic on r(u); the increment that lifts r(u) over its threshold
+//   enqueues u.
 //   Entries of degree <= kHubDeg are expanded per block (256 entries, degrees
 //   scanned in LDS); larger ones are cut into kHubPiece-edge pieces that any
 //   block may take.
@@ -22,8 +27,8 @@
 //   and the reverse graph stores in-neighbours by rank, so the gathers of
 //   high-degree nodes' increments (the most frequent ones) share lines.
 //   Queries are taken in groups of G = pull_group_for(batch) (16 for
-//   large batches), whose increments for one node form one unit (64 bytes
-//   at G = 16): a pull reads each in-edge's source once per group, so the
+//   large batches), whose increments for one node form one unit (128 bytes,
+//   one line, at G = 16): a pull reads each in-edge's source once per group, so the
 //   random reads per in-edge do not grow with the number of pulling
 //   queries.
 //   Nodes of in-degree above kHubDeg are summed in pieces by any block and
@@ -42,43 +47,43 @@ __device__ __forceinline__ size_t incd_index(int b, int32_t rk, int n, int G) {
 
 // The G increments of unit w of a group's rows.
 template <int G>
-__device__ __forceinline__ void load_unit(const float* __restrict__ grow, int32_t w,
-                                          float (&v)[G]) {
+__device__ __forceinline__ void load_unit(const u64* __restrict__ grow, int32_t w,
+                                          u64 (&v)[G]) {
   if constexpr (G == 1) {
     v[0] = grow[w];
   } else {
-    static_assert(G % 4 == 0, "units of four");
-    const float4* u = reinterpret_cast<const float4*>(grow) + (size_t)w * (G / 4);
+    static_assert(G % 2 == 0, "units of two");
+    const ulonglong2* u = reinterpret_cast<const ulonglong2*>(grow) + (size_t)w * (G / 2);
 #pragma unroll
-    for (int h = 0; h < G / 4; ++h) {
-      const float4 x = u[h];
-      v[4 * h] = x.x;
-      v[4 * h + 1] = x.y;
-      v[4 * h + 2] = x.z;
-      v[4 * h + 3] = x.w;
+    for (int h = 0; h < G / 2; ++h) {
+      const ulonglong2 x = u[h];
+      v[2 * h] = x.x;
+      v[2 * h + 1] = x.y;
     }
   }
 }
 constexpr unsigned kQueueCap = 1024;  // LDS-staged next-frontier entries per block
 
-// FORA_BALANCE before round 0 (nothing pushed): stop at once iff the
-// estimated walk cost (1 - alpha) omega_unit walk_cost is not positive.
-__device__ __forceinline__ bool balance_met(const QueryDev& q, u64 edge_ops, double mass) {
+// FORA_BALANCE: the push stops once its residue increments reach the
+// estimated walk cost (1 - alpha mass) (1 - alpha) omega_unit walk_cost, with
+// mass the residue pushed so far (an exact integer sum of fixed-point x).
+__device__ __forceinline__ bool balance_met(const QueryDev& q, u64 edge_ops, u64 mass_fx) {
+  const double mass = fx_to_double(mass_fx);
   const double est = (1.0 - q.alpha * mass) * (1.0 - q.alpha) * q.omega_unit * q.walk_cost;
   return (double)edge_ops >= est;
 }
 
-__global__ void k_init_queries(const QueryDev* Q, int batch, int n, const int2* info, float* r,
+__global__ void k_init_queries(const QueryDev* Q, int batch, int n, const int2* info, u64* r,
                                u64* fr0, Ctrl* ctrl, int32_t* stop, StatSlot* slots) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
   const int s = Q[b].src;
-  r[(size_t)b * n + s] = 1.0f;
-  if ((Q[b].flags & FORA_BALANCE) && balance_met(Q[b], 0, 0.0)) {
+  r[(size_t)b * n + s] = kFxOne;
+  if ((Q[b].flags & FORA_BALANCE) && balance_met(Q[b], 0, 0ull)) {
     stop[b] = 1;
     slots[(size_t)b * kStatSlots].balance_stopped = 1;
   }
-  if (1.0 > Q[b].rmax * (double)info[s].y) {
+  if (kFxOne > fx_threshold(Q[b].rmax, info[s].y)) {
     const u64 pos = atomicAdd(&ctrl->fr_cnt[0], 1ull);
     fr0[pos] = ((u64)b << 32) | (uint32_t)s;
   }
@@ -91,21 +96,22 @@ hipError_t launch_init_queries(const GraphDev& g, const Ws& w, int batch, hipStr
 }
 
 // Source distributions (the paper's extension of Algorithm 1): the initial
-// residue is sigma instead of e_s; q starts at zero (the zero-filled rows).
+// residue is sigma (rounded to the fixed point) instead of e_s; q starts at
+// zero (the zero-filled rows). An entry outside [0, 1] is flagged.
 __global__ void k_init_dist(const double* __restrict__ sigma, const QueryDev* Q, int batch,
-                            int n, float* r, Ctrl* ctrl, int32_t* stop, StatSlot* slots) {
+                            int n, u64* r, Ctrl* ctrl, int32_t* stop, StatSlot* slots) {
   const u64 total = (u64)batch * (u64)n;
   bool bad = false;
   for (u64 gi = (u64)blockIdx.x * blockDim.x + threadIdx.x; gi < total;
        gi += (u64)gridDim.x * blockDim.x) {
     const double x = sigma[gi];
-    const bool ok = x >= 0.0 && isfinite(x);
+    const bool ok = x >= 0.0 && x <= 1.0;  // false for NaN
     bad |= !ok;
-    r[gi] = ok ? (float)x : 0.0f;
+    r[gi] = ok ? fx_from_double(x) : 0ull;
   }
   if (bad) atomicOr(&ctrl->error, kErrBadDist);
   const u64 b = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < (u64)batch && (Q[b].flags & FORA_BALANCE) && balance_met(Q[b], 0, 0.0)) {
+  if (b < (u64)batch && (Q[b].flags & FORA_BALANCE) && balance_met(Q[b], 0, 0ull)) {
     stop[b] = 1;
     slots[b * kStatSlots].balance_stopped = 1;
   }
@@ -125,8 +131,8 @@ hipError_t launch_init_dist(const GraphDev& g, const Ws& w, const Layout& L, int
 // Per-query counters are staged in LDS (dynamic: 12 bytes per query) and
 // added to the block's stat slot and to this round's frontier-edge slot.
 __global__ __launch_bounds__(256) void k_push_snapshot(
-    int t, Ctrl* ctrl, const u64* __restrict__ fr_in, float* __restrict__ frx,
-    float* __restrict__ r, float* __restrict__ q, float* __restrict__ incd,
+    int t, Ctrl* ctrl, const u64* __restrict__ fr_in, u64* __restrict__ frx,
+    u64* __restrict__ r, float* __restrict__ q, u64* __restrict__ incd,
     const QueryDev* __restrict__ Q, StatSlot* slots, u64* ecnt, const int2* __restrict__ info,
     const int32_t* __restrict__ rank, const int32_t* __restrict__ stop, int n, int batch,
     int32_t* frontier_log, int64_t log_cap, u64 cap, u64* hub_idx,
@@ -153,14 +159,15 @@ __global__ __launch_bounds__(256) void k_push_snapshot(
     const int v = (int)(uint32_t)e;
     if (stop[b] != 0 && t + 1 >= stop[b]) continue;  // the balance rule ended this push
     const size_t gi = (size_t)b * n + v;
-    const float x = r[gi];
-    r[gi] = 0.0f;
+    const u64 x_fx = r[gi];
+    r[gi] = 0ull;
     if (Q[b].flags & FORA_BALANCE)
-      atomicAdd(&slots[(size_t)b * kStatSlots + (blockIdx.x & (kStatSlots - 1))].mass, (double)x);
+      atomicAdd(&slots[(size_t)b * kStatSlots + (blockIdx.x & (kStatSlots - 1))].mass_fx, x_fx);
     const double alpha = Q[b].alpha;
-    q[gi] = (float)((double)q[gi] + alpha * (double)x);
+    const double x = fx_to_double(x_fx);
+    q[gi] = (float)((double)q[gi] + alpha * x);
     const int d = info[v].y;
-    const float inc = (float)(((1.0 - alpha) * (double)x) / (double)d);
+    const u64 inc = fx_from_double(((1.0 - alpha) * x) / (double)d);
     frx[i] = inc;
     incd[incd_index(b, rank[v], n, pull_group_for(batch))] = inc;
     if (d > kHubDeg) {
@@ -219,11 +226,10 @@ __global__ __launch_bounds__(256) void k_push_mode(int t, Ctrl* ctrl, u64* ecnt,
       if (pull) slots[(size_t)b * kStatSlots].pull_rounds += 1;
       // FORA_BALANCE: the test before round t+1, over everything pushed so far
       if ((Q[b].flags & FORA_BALANCE) && stop[b] == 0) {
-        u64 fc = 0;
-        double mass = 0.0;
+        u64 fc = 0, mass = 0;
         for (int k = 0; k < kStatSlots; ++k) {
           fc += slots[(size_t)b * kStatSlots + k].edge_ops;
-          mass += slots[(size_t)b * kStatSlots + k].mass;
+          mass += slots[(size_t)b * kStatSlots + k].mass_fx;
         }
         if (balance_met(Q[b], fc, mass)) {
           stop[b] = t + 2;
@@ -284,16 +290,16 @@ struct NextQueue {
 
 // Apply one residue increment in push mode; the increment that lifts r(u)
 // over its threshold enqueues u.
-__device__ __forceinline__ void push_edge(int b, int u, float inc, double rmax,
-                                          float* __restrict__ r, int n,
+__device__ __forceinline__ void push_edge(int b, int u, u64 inc, double rmax, u64 thr1,
+                                          u64* __restrict__ r, int n,
                                           const int2* __restrict__ info, const NextQueue& nq) {
   const size_t gi = (size_t)b * n + u;
-  const float old = unsafeAtomicAdd(&r[gi], inc);
-  const float now = old + inc;
-  // every threshold is at least r_max (d >= 1): cheap pre-filter
-  if ((double)now > rmax) {
-    const double thr = rmax * (double)info[u].y;
-    if ((double)old <= thr && (double)now > thr) nq.push(((u64)b << 32) | (uint32_t)u);
+  const u64 old = atomicAdd(&r[gi], inc);
+  const u64 now = old + inc;
+  // every threshold is at least the degree-1 one (d >= 1): cheap pre-filter
+  if (now > thr1) {
+    const u64 thr = fx_threshold(rmax, info[u].y);
+    if (old <= thr && now > thr) nq.push(((u64)b << 32) | (uint32_t)u);
   }
 }
 
@@ -304,20 +310,20 @@ __device__ __forceinline__ void push_edge(int b, int u, float inc, double rmax,
 // increment into its LDS row.
 template <int G>
 __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
-    int t, Ctrl* ctrl, u64* __restrict__ fr_out, u64 cap, float* __restrict__ r,
-    const float* __restrict__ incd, const QueryDev* __restrict__ Q,
+    int t, Ctrl* ctrl, u64* __restrict__ fr_out, u64 cap, u64* __restrict__ r,
+    const u64* __restrict__ incd, const QueryDev* __restrict__ Q,
     const int32_t* __restrict__ pull_list, const int2* __restrict__ info,
     const int32_t* __restrict__ in_rowptr, const int32_t* __restrict__ in_colidx,
     const int32_t* __restrict__ inhub_node, const u64* __restrict__ inhub_base, int n_inhubs,
     u64 inhub_pieces, int n) {
   __shared__ u64 s_pre[kScatterBlock];
   __shared__ int32_t s_start[kScatterBlock];
-  __shared__ float s_sum[G][kScatterBlock];
+  __shared__ u64 s_sum[G][kScatterBlock];
   __shared__ u64 s_queue[kQueueCap];
   __shared__ unsigned s_qn;
   __shared__ u64 s_qbase;
   __shared__ u64 s_tmp[kScatterBlock / 64];
-  __shared__ float s_tmpf[kScatterBlock / 64];
+  __shared__ u64 s_tmpu[kScatterBlock / 64];
   (void)t;
   const int ngroups = ctrl->npull;
   if (ngroups == 0) return;  // uniform
@@ -333,7 +339,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
     const int32_t entry = pull_list[gidx];
     const int grp = entry >> 16;
     const unsigned mask = (unsigned)entry & 0xFFFFu;
-    const float* grow = incd + (size_t)grp * n * G;
+    const u64* grow = incd + (size_t)grp * n * G;
     if (is_chunk) {
       const u64 j = it % chunks;
       const int u0 = (int)(j * kScatterBlock);
@@ -344,7 +350,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
         s_start[threadIdx.x] = a;
         deg = (c - a) > kHubDeg ? 0ull : (u64)(c - a);
       }
-      for (int g = 0; g < G; ++g) s_sum[g][threadIdx.x] = 0.0f;
+      for (int g = 0; g < G; ++g) s_sum[g][threadIdx.x] = 0ull;
       u64 total;
       const u64 pre = block_exclusive_scan(deg, s_tmp, total);
       s_pre[threadIdx.x] = pre;
@@ -365,14 +371,14 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
           else hi = mid - 1;
         }
         u64 run_end = lo < last ? s_pre[lo + 1] : total;
-        float acc[G];
+        u64 acc[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) acc[g] = 0.0f;
+        for (int g = 0; g < G; ++g) acc[g] = 0ull;
         auto flush = [&](int node) {
 #pragma unroll
           for (int g = 0; g < G; ++g) {
-            if (((mask >> g) & 1u) && acc[g] != 0.0f) atomicAdd(&s_sum[g][node], acc[g]);
-            acc[g] = 0.0f;
+            if (((mask >> g) & 1u) && acc[g] != 0ull) atomicAdd(&s_sum[g][node], acc[g]);
+            acc[g] = 0ull;
           }
         };
         for (; k < kend; ++k) {
@@ -381,7 +387,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
             ++lo;
             run_end = lo < last ? s_pre[lo + 1] : total;
           }
-          float v[G];
+          u64 v[G];
           load_unit<G>(grow, in_colidx[(int64_t)s_start[lo] + (int64_t)(k - s_pre[lo])], v);
 #pragma unroll
           for (int g = 0; g < G; ++g) acc[g] += v[g];
@@ -390,15 +396,15 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
       }
       __syncthreads();
       if (u < n) {
-        const double d_u = (double)info[u].y;
+        const int d_u = info[u].y;
         for (int g = 0; g < G; ++g) {
-          const float add = s_sum[g][threadIdx.x];
-          if (((mask >> g) & 1u) && add > 0.0f) {
+          const u64 add = s_sum[g][threadIdx.x];
+          if (((mask >> g) & 1u) && add != 0ull) {
             const int b = grp * G + g;
             const size_t gi = (size_t)b * n + u;
-            const float now = r[gi] + add;
+            const u64 now = r[gi] + add;
             r[gi] = now;
-            if ((double)now > Q[b].rmax * d_u) nq.push(((u64)b << 32) | (uint32_t)u);
+            if (now > fx_threshold(Q[b].rmax, d_u)) nq.push(((u64)b << 32) | (uint32_t)u);
           }
         }
       }
@@ -415,28 +421,28 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
       const int64_t a = in_rowptr[u], c = in_rowptr[u + 1];
       const int64_t first = a + (int64_t)(p - inhub_base[lo]) * kHubPiece;
       const int64_t end = first + kHubPiece < c ? first + kHubPiece : c;
-      float part[G];
+      u64 part[G];
 #pragma unroll
-      for (int g = 0; g < G; ++g) part[g] = 0.0f;
+      for (int g = 0; g < G; ++g) part[g] = 0ull;
       for (int64_t k = first + threadIdx.x; k < end; k += kScatterBlock) {
-        float v[G];
+        u64 v[G];
         load_unit<G>(grow, in_colidx[k], v);
 #pragma unroll
         for (int g = 0; g < G; ++g) part[g] += v[g];
       }
-      float sums[G];
+      u64 sums[G];
       for (int g = 0; g < G; ++g)
-        sums[g] = ((mask >> g) & 1u) ? block_sum(part[g], s_tmpf) : 0.0f;
+        sums[g] = ((mask >> g) & 1u) ? block_sum(part[g], s_tmpu) : 0ull;
       if (threadIdx.x == 0) {
-        const double d_u = (double)info[u].y;
+        const int d_u = info[u].y;
         for (int g = 0; g < G; ++g) {
-          if (!((mask >> g) & 1u) || !(sums[g] > 0.0f)) continue;
+          if (!((mask >> g) & 1u) || sums[g] == 0ull) continue;
           const int b = grp * G + g;
           const size_t gi = (size_t)b * n + u;
-          const float old = unsafeAtomicAdd(&r[gi], sums[g]);
-          const float now = old + sums[g];
-          const double thr = Q[b].rmax * d_u;
-          if ((double)old <= thr && (double)now > thr) nq.push(((u64)b << 32) | (uint32_t)u);
+          const u64 old = atomicAdd(&r[gi], sums[g]);
+          const u64 now = old + sums[g];
+          const u64 thr = fx_threshold(Q[b].rmax, d_u);
+          if (old <= thr && now > thr) nq.push(((u64)b << 32) | (uint32_t)u);
         }
       }
     }
@@ -450,8 +456,8 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
 }
 
 __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
-    int t, Ctrl* ctrl, const u64* __restrict__ fr_in, const float* __restrict__ frx,
-    u64* __restrict__ fr_out, u64 cap, float* __restrict__ r, float* __restrict__ incd,
+    int t, Ctrl* ctrl, const u64* __restrict__ fr_in, const u64* __restrict__ frx,
+    u64* __restrict__ fr_out, u64 cap, u64* __restrict__ r, u64* __restrict__ incd,
     const int32_t* __restrict__ mode, const int32_t* __restrict__ stop,
     const QueryDev* __restrict__ Q, const int2* __restrict__ info,
     const int32_t* __restrict__ colidx, const int32_t* __restrict__ rank, int n,
@@ -460,8 +466,9 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
   __shared__ u64 s_pre[kScatterBlock];
   __shared__ int32_t s_start[kScatterBlock];
   __shared__ uint32_t s_ent_b[kScatterBlock];
-  __shared__ float s_inc[kScatterBlock];
+  __shared__ u64 s_inc[kScatterBlock];
   __shared__ double s_rmax[kScatterBlock];
+  __shared__ u64 s_thr1[kScatterBlock];
   __shared__ u64 s_queue[kQueueCap];
   __shared__ unsigned s_qn;
   __shared__ u64 s_qbase;
@@ -482,7 +489,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
   for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
        i += (u64)gridDim.x * blockDim.x) {
     const u64 e = fr_in[i];
-    incd[incd_index((int)(e >> 32), rank[(uint32_t)e], n, pull_group)] = 0.0f;
+    incd[incd_index((int)(e >> 32), rank[(uint32_t)e], n, pull_group)] = 0ull;
   }
   __syncthreads();
 
@@ -502,12 +509,13 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
     if (mode[b]) continue;  // uniform per block: this query pulls this round
     const int v = (int)(uint32_t)e;
     const int2 inf = info[v];
-    const float inc = frx[i];
+    const u64 inc = frx[i];
     const double rmax = Q[b].rmax;
+    const u64 thr1 = fx_threshold(rmax, 1);
     const int64_t first = (int64_t)(p - hub_base[lo]) * kHubPiece;
     const int64_t last = first + kHubPiece < inf.y ? first + kHubPiece : inf.y;
     for (int64_t k = first + threadIdx.x; k < last; k += kScatterBlock)
-      push_edge(b, colidx[(int64_t)inf.x + k], inc, rmax, r, n, info, nq);
+      push_edge(b, colidx[(int64_t)inf.x + k], inc, rmax, thr1, r, n, info, nq);
     // all threads read the queue length after the barrier, so the decision
     // to flush (which contains barriers) is the same for the whole block
     __syncthreads();
@@ -530,6 +538,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
       s_ent_b[threadIdx.x] = (uint32_t)b;
       s_inc[threadIdx.x] = frx[i];
       s_rmax[threadIdx.x] = Q[b].rmax;
+      s_thr1[threadIdx.x] = fx_threshold(Q[b].rmax, 1);
       const bool skip = mode[b] || (stop[b] != 0 && t + 1 >= stop[b]);
       deg = (inf.y > kHubDeg || skip) ? 0ull : (u64)inf.y;
     }
@@ -548,7 +557,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
         else hi = mid - 1;
       }
       push_edge((int)s_ent_b[lo], colidx[(int64_t)s_start[lo] + (int64_t)(k - s_pre[lo])],
-                s_inc[lo], s_rmax[lo], r, n, info, nq);
+                s_inc[lo], s_rmax[lo], s_thr1[lo], r, n, info, nq);
     }
     nq.flush();
   }
@@ -557,7 +566,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(
 // Frontier from scratch: every (query, node) whose residue exceeds the
 // query's current threshold (used when a threshold is lowered mid-way).
 __global__ __launch_bounds__(256) void k_seed_frontier(int t, Ctrl* ctrl,
-                                                       const float* __restrict__ r,
+                                                       const u64* __restrict__ r,
                                                        const QueryDev* __restrict__ Q,
                                                        const int2* __restrict__ info, int n,
                                                        int batch, u64* fr, u64 cap) {
@@ -570,7 +579,7 @@ __global__ __launch_bounds__(256) void k_seed_frontier(int t, Ctrl* ctrl,
     if (gi < total) {
       b = (int)(gi / (u64)n);
       v = (int)(gi - (u64)b * n);
-      over = (double)r[gi] > Q[b].rmax * (double)info[v].y;
+      over = r[gi] > fx_threshold(Q[b].rmax, info[v].y);
     }
     const u64 mask = __ballot(over);
     u64 pos0 = 0;

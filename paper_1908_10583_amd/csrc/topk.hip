@@ -24,7 +24,7 @@ __device__ __forceinline__ bool prefix_ok(uint32_t key, int pass, uint32_t prefi
 
 __global__ __launch_bounds__(kTopkThreads) void k_topk_hist(
     int pass, const float* __restrict__ q, const u64* __restrict__ acc,
-    const float* __restrict__ r, const QueryDev* __restrict__ Q, float* __restrict__ pi,
+    const u64* __restrict__ r, const QueryDev* __restrict__ Q, float* __restrict__ pi,
     int n, uint32_t* hist, const uint32_t* sel, const Ctrl* ctrl) {
   __shared__ uint32_t s_hist[kHistBins];
   if (ctrl->skip) return;
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk_hist(
     uint32_t key;
     if (pass == 0) {
       double p = (double)q[row + v] + (double)acc[row + v] * (1.0 / kFx);
-      if (zero_hop != 0.0) p += zero_hop * (double)r[row + v];
+      if (zero_hop != 0.0) p += zero_hop * fx_to_double(r[row + v]);
       const float pf = (float)p;
       pi[row + v] = pf;
       key = __float_as_uint(pf);

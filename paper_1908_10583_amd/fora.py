@@ -62,7 +62,7 @@ class fora_tuning(ctypes.Structure):
 
 
 class fora_views(ctypes.Structure):
-    _fields_ = [("residue", ctypes.c_void_p), ("reserve", ctypes.c_void_p),
+    _fields_ = [("residue_fx", ctypes.c_void_p), ("reserve", ctypes.c_void_p),
                 ("walk_count", ctypes.c_void_p), ("walk_weight_fx", ctypes.c_void_p),
                 ("pi_hat", ctypes.c_void_p)]
 
@@ -232,7 +232,9 @@ def workspace(g: Graph, batch: int = 1) -> torch.Tensor:
 
 
 def fora_workspace_views(g: Graph, batch: int, ws: torch.Tensor) -> dict:
-    """Tensors aliasing the dense per-query arrays inside ``ws`` (rows of n)."""
+    """Tensors aliasing the dense per-query arrays inside ``ws`` (rows of n),
+    plus ``residue``: a float64 copy of the fixed-point residues (exact where
+    the residue has at most 53 significant bits, else rounded to nearest)."""
     v = fora_views()
     _check(_lib.fora_workspace_views(g.handle, batch, _ptr(ws), ctypes.byref(v)))
     base = ws.data_ptr()
@@ -242,7 +244,9 @@ def fora_workspace_views(g: Graph, batch: int, ws: torch.Tensor) -> dict:
         off = p - base
         return ws[off:off + cap * itemsize].view(dtype).view(batch, g.n)
 
-    return dict(residue=view(v.residue, torch.float32, 4),
+    residue_fx = view(v.residue_fx, torch.int64, 8)  # uint64 bits, values below 2^63
+    return dict(residue_fx=residue_fx,
+                residue=residue_fx.double() * 2.0**-62,
                 reserve=view(v.reserve, torch.float32, 4),
                 walk_count=view(v.walk_count, torch.int64, 8),        # uint64 bits
                 walk_weight_fx=view(v.walk_weight_fx, torch.int64, 8),  # uint64 bits
