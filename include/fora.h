@@ -208,6 +208,25 @@ int fora_ssppr(const fora_graph *g, int32_t src, double alpha, double eps,
                int32_t *d_topk_ids, float *d_topk_vals, fora_stats *h_stats,
                void *stream);
 
+/* fora_ssppr for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc). The
+ * workspace is a static device array of FORA_STATIC_SCRATCH_BYTES that the
+ * library holds on every device it runs on until the process ends; the call
+ * makes no hipMalloc or hipFree, captures no HIP graph (graph_rounds is
+ * ignored) and records no events (the ms_* fields of the stats are 0). The
+ * caller passes only the outputs. Every call on a device shares that
+ * device's array, which keeps the last call's contents (each call clears
+ * what must start at zero): calls that overlap on one device race, so order
+ * them (one stream, or synchronise). The array's device address is looked
+ * up on the first call on each device. Results equal fora_ssppr's bit for
+ * bit. FORA_E_NOMEM if the graph needs more workspace than the array holds
+ * (fora_workspace_size(g, 1) > FORA_STATIC_SCRATCH_BYTES: graphs up to
+ * about 1.4 million nodes fit); other errors as fora_ssppr. */
+#define FORA_STATIC_SCRATCH_BYTES (128u << 20)
+int fora_ssppr_static(const fora_graph *g, int32_t src, double alpha, double eps, double delta,
+                      double pf, int32_t k, double opt_rmax, uint64_t seed, int32_t *d_topk_ids,
+                      float *d_topk_vals, fora_stats *h_stats, void *stream);
+
 /* The same for `batch` queries in one launch sequence: all queries' push
  * rounds, walk plans, walks and selections run in shared kernels. Query b's
  * result is written to d_ids[b*kmax ...], d_vals[b*kmax ...]; kmax must be at

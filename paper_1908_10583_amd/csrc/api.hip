@@ -390,9 +390,11 @@ int run_queries_graph(fora_graph* g, const Call& c, int batch, const std::vector
 }
 
 // d_sigma (nullable): double[batch][n], each query's source distribution
+// eager_only: never capture or replay a HIP graph, and time no phases (the
+// allocation-free entry point: both would allocate)
 int run_queries(fora_graph* g, int batch, const fora_query* qs, int kmax, void* d_ws,
                 size_t ws_bytes, int32_t* d_ids, float* d_vals, fora_stats* h_stats,
-                hipStream_t s, const double* d_sigma = nullptr) {
+                hipStream_t s, const double* d_sigma = nullptr, bool eager_only = false) {
   if (!qs) return fail(FORA_E_ARG, "null queries");
   if (!d_ids || !d_vals) return fail(FORA_E_ARG, "null output");
   Call c;
@@ -410,12 +412,12 @@ int run_queries(fora_graph* g, int batch, const fora_query* qs, int kmax, void* 
   c.walk_chunk = all_index ? std::max(walk_chunk(g), kIndexWalkChunk) : walk_chunk(g);
   c.index_only = all_index;
   FORA_HIP(hipSetDevice(g->device));
-  if (g->tuning.graph_rounds > 0 && !d_sigma)
+  if (g->tuning.graph_rounds > 0 && !d_sigma && !eager_only)
     return run_queries_graph(g, c, batch, qd, kmax, d_ws, d_ids, d_vals, h_stats, s);
   FORA_HIP(launch_fill_zero((char*)d_ws + c.L.zero_begin, c.L.zero_end - c.L.zero_begin, s));
   FORA_HIP(hipMemcpyAsync(c.w.queries, qd.data(), sizeof(QueryDev) * batch,
                           hipMemcpyHostToDevice, s));
-  PhaseEvents pe(h_stats != nullptr);
+  PhaseEvents pe(h_stats != nullptr && !eager_only);
   pe.mark(0, s);
   if (d_sigma)
     FORA_HIP(launch_init_dist(g->dev, c.w, c.L, batch, d_sigma, s));
@@ -695,6 +697,35 @@ int build_records(fora_graph* g, int mode, hipStream_t s) {
   return FORA_OK;
 }
 
+// ---- workspace for callers that cannot allocate -----------------------------
+// A file-scope device array that fora_ssppr_static uses as its workspace. Each
+// device holds its own copy from the time the library's code is loaded on it
+// until the process ends. Host code never passes the array's name to a kernel
+// (on the host it is a stand-in, not a device address): the device address is
+// looked up once per device with hipGetSymbolAddress and kept here.
+constexpr size_t kStaticScratchBytes = (size_t)FORA_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's device address on the current device (looked up on
+// the first call made with that device current).
+int static_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(FORA_E_ARG, "device id out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FORA_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return FORA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -862,6 +893,32 @@ int fora_ssppr(const fora_graph* g, int32_t src, double alpha, double eps, doubl
   q.seed = seed;
   return run_queries(const_cast<fora_graph*>(g), 1, &q, k, d_ws, ws_bytes, d_topk_ids,
                      d_topk_vals, h_stats, (hipStream_t)stream);
+}
+
+int fora_ssppr_static(const fora_graph* g, int32_t src, double alpha, double eps, double delta,
+                      double pf, int32_t k, double opt_rmax, uint64_t seed, int32_t* d_topk_ids,
+                      float* d_topk_vals, fora_stats* h_stats, void* stream) {
+  if (!g) return fail(FORA_E_ARG, "null graph");
+  const size_t need = make_layout(g->dev, 1).total;
+  if (need > kStaticScratchBytes)
+    return fail(FORA_E_NOMEM, "the graph needs " + std::to_string(need) +
+                                  " bytes of workspace, above the static scratch of " +
+                                  std::to_string(kStaticScratchBytes) + " bytes");
+  FORA_HIP(hipSetDevice(g->device));
+  void* ws = nullptr;
+  const int rc = static_scratch(g->device, &ws);
+  if (rc != FORA_OK) return rc;
+  fora_query q{};
+  q.src = src;
+  q.k = k;
+  q.alpha = alpha;
+  q.eps = eps;
+  q.delta = delta;
+  q.pf = pf;
+  q.rmax = opt_rmax;
+  q.seed = seed;
+  return run_queries(const_cast<fora_graph*>(g), 1, &q, k, ws, kStaticScratchBytes, d_topk_ids,
+                     d_topk_vals, h_stats, (hipStream_t)stream, nullptr, true);
 }
 
 int fora_ssppr_batch(const fora_graph* g, int32_t batch, const fora_query* h_queries,

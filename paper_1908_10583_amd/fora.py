@@ -87,6 +87,8 @@ def _load():
         "fora_workspace_views": ([P, I32, P, ctypes.POINTER(fora_views)], ctypes.c_int),
         "fora_ssppr": ([P, I32, F64, F64, F64, F64, I32, F64, U64, P, SZ, P, P,
                         ctypes.POINTER(fora_stats), P], ctypes.c_int),
+        "fora_ssppr_static": ([P, I32, F64, F64, F64, F64, I32, F64, U64, P, P,
+                               ctypes.POINTER(fora_stats), P], ctypes.c_int),
         "fora_ssppr_batch": ([P, I32, ctypes.POINTER(fora_query), I32, P, SZ, P, P,
                               ctypes.POINTER(fora_stats), P], ctypes.c_int),
         "fora_dist_batch": ([P, I32, ctypes.POINTER(fora_query), P, I32, P, SZ, P, P,
@@ -127,7 +129,8 @@ _lib = _load()
 
 EXPORTED = ["fora_last_error", "fora_build_csr", "fora_free_graph", "fora_graph_info",
             "fora_get_tuning", "fora_set_tuning",
-            "fora_workspace_size", "fora_workspace_views", "fora_ssppr", "fora_ssppr_batch",
+            "fora_workspace_size", "fora_workspace_views", "fora_ssppr", "fora_ssppr_static",
+            "fora_ssppr_batch",
             "fora_dist_batch",
             "fora_push_only", "fora_walk_only", "fora_philox", "fora_features",
             "fora_mlp_forward", "fora_mlp_backward", "fora_adam_step", "fora_mlp_to_bf16",
@@ -287,6 +290,32 @@ def fora_ssppr(g: Graph, src: int, alpha: float = 0.2, eps: float = 0.5,
                            _ptr(ws), ws.numel(), _ptr(ids), _ptr(vals),
                            ctypes.byref(st) if st is not None else None,
                            ctypes.c_void_p(_stream(stream))))
+    return Result(ids, vals, st.as_dict() if st is not None else None)
+
+
+FORA_STATIC_SCRATCH_BYTES = 128 << 20
+
+
+def fora_ssppr_static(g: Graph, src: int, alpha: float = 0.2, eps: float = 0.5,
+                      delta: float | None = None, pf: float | None = None, k: int = 500,
+                      rmax: float | None = None, seed: int = 0, stats: bool = False,
+                      out: tuple | None = None, stream=None) -> Result:
+    """One query with the library's static device workspace: the call itself
+    allocates no device memory (the outputs are allocated here unless
+    ``out`` is given)."""
+    delta = 1.0 / g.n if delta is None else delta
+    pf = 1.0 / g.n if pf is None else pf
+    if out is None:
+        ids = torch.empty(k, dtype=torch.int32, device=g.device)
+        vals = torch.empty(k, dtype=torch.float32, device=g.device)
+    else:
+        ids, vals = out
+    st = fora_stats() if stats else None
+    _check(_lib.fora_ssppr_static(g.handle, int(src), alpha, eps, delta, pf, int(k),
+                                  0.0 if rmax is None else float(rmax),
+                                  int(seed) & (2**64 - 1), _ptr(ids), _ptr(vals),
+                                  ctypes.byref(st) if st is not None else None,
+                                  ctypes.c_void_p(_stream(stream))))
     return Result(ids, vals, st.as_dict() if st is not None else None)
 
 

@@ -49,3 +49,13 @@ def test_argument_errors_need_no_gpu():
                               ctypes.byref(out)) == fora.FORA_E_ARG
     sz = ctypes.c_size_t()
     assert lib.fora_workspace_size(None, 1, ctypes.byref(sz)) == fora.FORA_E_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfora.so not built")
+def test_static_entry_point_checks_its_arguments_on_the_host():
+    from paper_1908_10583_amd import fora
+    text = open(HEADER).read()
+    m = re.search(r"#define FORA_STATIC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == fora.FORA_STATIC_SCRATCH_BYTES
+    assert fora._lib.fora_ssppr_static(None, 0, 0.2, 0.5, 1e-3, 1e-3, 1, 0.0, 0, None, None,
+                                       None, None) == fora.FORA_E_ARG
