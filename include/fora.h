@@ -89,13 +89,13 @@ typedef struct fora_query {
   double walk_cost;  /* FORA_BALANCE: cost of one walk in residue increments */
 } fora_query;
 
-/* Algorithm 3 (section 5), per query:
- * FORA_PRUNE_ZERO_HOP (section 5.1): pi_hat starts at q + alpha r; from each
+/* Algorithm 3 (section 4), per query:
+ * FORA_PRUNE_ZERO_HOP (section 4.1): pi_hat starts at q + alpha r; from each
  *   v with residue, omega_v = ceil(r'(v) omega_unit) walks with
  *   r' = (1 - alpha) r (FP64 from the fixed-point residue), each starting with a
  *   forced move (the step-0 Philox block only picks the out-neighbour) and
  *   adding r'(v) / omega_v at its end point.
- * FORA_BALANCE (section 5.2): before each push round the push stops once its
+ * FORA_BALANCE (section 4.2): before each push round the push stops once its
  *   residue increments so far reach the estimated walk cost
  *   (1 - alpha * pushed mass) (1 - alpha) omega_unit walk_cost; r_max still
  *   bounds the push from below. */
@@ -247,8 +247,8 @@ int fora_ssppr_batch(const fora_graph *g, int32_t batch,
                      size_t ws_bytes, int32_t *d_ids, float *d_vals,
                      fora_stats *h_stats, void *stream);
 
-/* FORA for source distributions (the paper's extension to source
- * distributions; global PageRank is sigma = (1/n, ..., 1/n)): query b's push
+/* FORA for source distributions (section 6.2, the extension to source
+ * distributions; global PageRank, section 6.3, is sigma = (1/n, ..., 1/n)): query b's push
  * starts from r = sigma_b instead of e_s, which keeps the invariant
  * pi(sigma, t) = q(t) + sum_v r(v) pi(v, t), so walks, estimate and top-k are
  * those of fora_ssppr_batch and the eps guarantee holds for pi(sigma, .).
@@ -283,7 +283,7 @@ int fora_index_info(const fora_graph *g, int64_t *total, double *alpha,
 /* Copies the index: d_off uint64[n + 1] and d_dest int32[total] (device). */
 int fora_index_export(const fora_graph *g, uint64_t *d_off, int32_t *d_dest, void *stream);
 
-/* ---- top-k FORA (Algorithm 5, section 6.2) ------------------------------
+/* ---- top-k FORA (Algorithm 5, section 5.2) ------------------------------
  * For each query, with its own k: run Algorithm 2 with eps' = eps / 2,
  * p_f' = p_f / (n max(log2(n / k), 1)) and delta = 1/k, 1/(2k), ... (while
  * above 1/n, then 1/n), r_max by eqn:rmax for those parameters unless the
@@ -305,14 +305,16 @@ int fora_topk_batch(const fora_graph *g, int32_t batch, const fora_query *h_quer
 /* ---- step-level entry points (used to compare each phase on its own) ---- */
 
 /* Only the push phase of fora_ssppr for one source (Algorithm 1,
- * synchronous rounds). Results in the workspace views (row 0).
+ * synchronous rounds), or, with d_sigma (nullable, double[n], device) given,
+ * of fora_dist_batch for that source distribution (src is then not used).
+ * Results in the workspace views (row 0).
  * h_round_sizes (nullable, max_rounds entries) receives |F_t|; d_frontiers
  * (nullable, device int32, frontier_cap entries) receives the frontiers of
  * all rounds back to back, each round's set in ascending id order.
  * Waits for completion. FORA_E_OVERFLOW if max_rounds or frontier_cap is too
  * small. */
 int fora_push_only(const fora_graph *g, int32_t src, double alpha, double rmax,
-                   void *d_ws, size_t ws_bytes, int32_t max_rounds,
+                   const double *d_sigma, void *d_ws, size_t ws_bytes, int32_t max_rounds,
                    int32_t *h_round_sizes, int32_t *d_frontiers,
                    int64_t frontier_cap, fora_stats *h_stats, void *stream);
 
@@ -329,6 +331,11 @@ int fora_walk_only(const fora_graph *g, int64_t entries, const int32_t *d_v,
                    const uint64_t *d_omega, const double *d_w, uint32_t key0,
                    uint32_t key1, double alpha, void *d_ws, size_t ws_bytes,
                    uint64_t *h_steps, void *stream);
+
+/* The graph's degree rank (copied to d_rank, int32[n], device): rank[v] is
+ * v's position when nodes are ordered by out-degree descending, ties by id
+ * ascending. It orders the walk records and the pull increments. Waits. */
+int fora_graph_rank(const fora_graph *g, int32_t *d_rank, void *stream);
 
 /* Philox4x32-10 (Salmon et al., SC'11) blocks on the device: d_out[4i..4i+3]
  * = Philox(d_ctr[4i..4i+3], (key0, key1)). */

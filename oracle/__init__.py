@@ -294,11 +294,11 @@ def fora(g, s: int, alpha: float = 0.2, eps: float = 0.5, delta: float | None = 
          walk_cost: float | None = None, walk_key=None) -> dict:
     """Whole-graph FORA (Algorithm 2) followed by top-k selection.
 
-    prune: Algorithm 3's zero-hop pruning (section 5.1): pi_hat starts at
+    prune: Algorithm 3's zero-hop pruning (section 4.1): pi_hat starts at
     q + alpha r, and from each v with residue ceil(r'(v) omega_unit) walks
     with r' = (1 - alpha) r start at a random out-neighbour of v, each adding
     r'(v) / omega_v at its end point.
-    walk_cost: Algorithm 3's balance rule (section 5.2), the cost of one walk
+    walk_cost: Algorithm 3's balance rule (section 4.2), the cost of one walk
     in edge-operation units (None: plain Algorithm 1).
     walk_key: (key0, key1) of the walks instead of (s, seed): the walks of an
     index shared by all sources (FORA+, section 3.3); walk j from v is then
@@ -332,7 +332,7 @@ DIST_KEY0 = 0xFFFFFFFF  # first Philox key word of walks for a source distributi
 def fora_dist(g, sigma, alpha: float = 0.2, eps: float = 0.5, delta: float | None = None,
               pf: float | None = None, k: int = 500, seed: int = 0,
               rmax: float | None = None, log_frontiers: bool = False) -> dict:
-    """FORA for a source distribution sigma (the paper's appendix on source
+    """FORA for a source distribution sigma (section 6.2, the paper's extension to source
     distributions): Algorithm 1 starts from r = sigma, q = 0 instead of
     r = e_s, which keeps the invariant pi(sigma, t) = q(t) + sum_v r(v)
     pi(v, t); Algorithm 2 and the selection are unchanged. Global PageRank is

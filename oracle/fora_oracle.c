@@ -151,7 +151,7 @@ static double push_round(const int32_t *rowptr, const int32_t *colidx, double al
 /* The push loop from a given (r, q), so that Algorithm 1 can be continued  */
 /* at a lower threshold from the state another threshold left.              */
 /* With walk_cost >= 0 it also applies the balance rule of Algorithm 3      */
-/* (section 5.2): before each round, with FC the edge operations done so    */
+/* (section 4.2): before each round, with FC the edge operations done so    */
 /* far and r_sum = 1 - alpha * (mass pushed so far), it stops once          */
 /* FC >= r_sum (1 - alpha) omega_unit walk_cost, the estimated cost of the  */
 /* walks in edge-operation units. *balance_margin (if given) receives the   */

@@ -1163,22 +1163,22 @@ int fora_topk_batch(const fora_graph* gc, int32_t batch, const fora_query* h_que
   return FORA_OK;
 }
 
-int fora_push_only(const fora_graph* gc, int32_t src, double alpha, double rmax, void* d_ws,
-                   size_t ws_bytes, int32_t max_rounds, int32_t* h_round_sizes,
-                   int32_t* d_frontiers, int64_t frontier_cap, fora_stats* h_stats,
-                   void* stream) {
+int fora_push_only(const fora_graph* gc, int32_t src, double alpha, double rmax,
+                   const double* d_sigma, void* d_ws, size_t ws_bytes, int32_t max_rounds,
+                   int32_t* h_round_sizes, int32_t* d_frontiers, int64_t frontier_cap,
+                   fora_stats* h_stats, void* stream) {
   fora_graph* g = const_cast<fora_graph*>(gc);
   hipStream_t s = (hipStream_t)stream;
   Call c;
   int rc = prepare(g, 1, d_ws, ws_bytes, c);
   if (rc != FORA_OK) return rc;
-  if (src < 0 || src >= g->dev.n) return fail(FORA_E_ARG, "source out of range");
+  if (!d_sigma && (src < 0 || src >= g->dev.n)) return fail(FORA_E_ARG, "source out of range");
   if (!(alpha > 0.0 && alpha < 1.0)) return fail(FORA_E_ARG, "alpha must be in (0,1)");
   if (!(rmax > 0.0 && std::isfinite(rmax))) return fail(FORA_E_ARG, "rmax must be > 0");
   if (max_rounds < 0) return fail(FORA_E_ARG, "max_rounds < 0");
   if (d_frontiers && frontier_cap < 0) return fail(FORA_E_ARG, "frontier_cap < 0");
   QueryDev qd{};
-  qd.src = src;
+  qd.src = d_sigma ? 0 : src;
   qd.k = 1;
   qd.alpha = alpha;
   qd.rmax = rmax;
@@ -1186,7 +1186,10 @@ int fora_push_only(const fora_graph* gc, int32_t src, double alpha, double rmax,
   FORA_HIP(hipSetDevice(g->device));
   FORA_HIP(launch_fill_zero((char*)d_ws + c.L.zero_begin, c.L.zero_end - c.L.zero_begin, s));
   FORA_HIP(hipMemcpyAsync(c.w.queries, &qd, sizeof(qd), hipMemcpyHostToDevice, s));
-  FORA_HIP(launch_init_queries(g->dev, c.w, 1, s));
+  if (d_sigma)
+    FORA_HIP(launch_init_dist(g->dev, c.w, c.L, 1, d_sigma, s));
+  else
+    FORA_HIP(launch_init_queries(g->dev, c.w, 1, s));
   int rounds = 0;
   rc = run_push(g, c, 1, s, true, d_frontiers, d_frontiers ? frontier_cap : 0, &rounds);
   if (rc != FORA_OK) return rc;
@@ -1402,6 +1405,15 @@ int fora_push_sweep(const fora_graph* gc, int32_t batch, const fora_query* h_que
   int flags = 0;
   FORA_HIP(hipMemcpy(&flags, &c.w.ctrl->error, sizeof(int), hipMemcpyDeviceToHost));
   return error_code_from_flags(flags);
+}
+
+int fora_graph_rank(const fora_graph* g, int32_t* d_rank, void* stream) {
+  if (!g || !d_rank) return fail(FORA_E_ARG, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  FORA_HIP(hipMemcpyAsync(d_rank, g->dev.rank, sizeof(int32_t) * (size_t)g->dev.n,
+                          hipMemcpyDeviceToDevice, s));
+  FORA_HIP(hipStreamSynchronize(s));
+  return FORA_OK;
 }
 
 int fora_philox(int64_t count, const uint32_t* d_ctr, uint32_t key0, uint32_t key1,

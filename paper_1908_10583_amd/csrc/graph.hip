@@ -1,7 +1,5 @@
 // Graph ingest checks, the per-node {row start, out-degree} table, a zero
 // fill, and the device Philox block kernel used for RNG checks.
-#include <hipcub/hipcub.hpp>
-
 #include "internal.h"
 #include "scan.h"
 
@@ -253,13 +251,99 @@ hipError_t launch_index_plan(const GraphDev& g, double walks_per_degree, u64* of
   return hipGetLastError();
 }
 
-// Degree rank: sort (out-degree, id) pairs by degree, descending (the sort is
-// stable, so equal degrees keep id order), then rank[order[i]] = i.
-__global__ void k_deg_keys(const int2* __restrict__ info, int32_t n, int32_t* key, int32_t* id) {
+// Degree rank: rank[v] = position of v when nodes are ordered by out-degree
+// descending, ties by id ascending. An LSD radix sort of the keys
+// (max_deg - d(v)) with the ids as values, 8-bit digits, as many passes as
+// max_deg has bytes; every pass is stable, so equal degrees keep id order.
+// A pass: per-tile digit histograms (digit-major, so one exclusive scan over
+// them gives each (digit, tile) its output start), then a scatter in which
+// each wave ranks its lanes among equal digits with eight ballots and the
+// waves of a block take their places in lane, wave and round order.
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 8;
+constexpr int kSortTile = kSortThreads * kSortRounds;  // elements per block
+
+__global__ void k_deg_keys(const int2* __restrict__ info, int32_t n, int32_t max_deg,
+                           uint32_t* key, int32_t* id) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
-    key[v] = info[v].y;
+    key[v] = (uint32_t)(max_deg - info[v].y);
     id[v] = (int32_t)v;
+  }
+}
+
+// element i of tile t sits at t * kSortTile + round * kSortThreads + thread
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __restrict__ key,
+                                                            int64_t n, int shift, int64_t tiles,
+                                                            uint32_t* hist) {
+  __shared__ uint32_t s_h[256];
+  s_h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = base + r * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&s_h[(key[i] >> shift) & 0xFFu], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * tiles + blockIdx.x] = s_h[threadIdx.x];
+}
+
+// Exclusive scan of `count` entries in place, one block.
+__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* a, int64_t count) {
+  __shared__ uint32_t s_tmp[1024 / 64];
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < count; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const uint32_t v = i < count ? a[i] : 0u;
+    uint32_t tot;
+    const uint32_t pre = block_exclusive_scan(v, s_tmp, tot);
+    if (i < count) a[i] = carry + pre;
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
+    const uint32_t* __restrict__ key_in, const int32_t* __restrict__ val_in, int64_t n, int shift,
+    int64_t tiles, const uint32_t* __restrict__ start, uint32_t* key_out, int32_t* val_out) {
+  __shared__ uint32_t s_base[256];
+  __shared__ uint32_t s_wcnt[kSortThreads / 64][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  s_base[threadIdx.x] = start[(size_t)threadIdx.x * tiles + blockIdx.x];
+  for (int w = 0; w < kSortThreads / 64; ++w) s_wcnt[w][threadIdx.x] = 0;
+  __syncthreads();
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = base + r * kSortThreads + threadIdx.x;
+    const bool valid = i < n;
+    const uint32_t k = valid ? key_in[i] : 0u;
+    const int32_t v = valid ? val_in[i] : 0;
+    const uint32_t d = (k >> shift) & 0xFFu;
+    // lanes of this wave holding the same digit
+    unsigned long long same = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const unsigned long long m = __ballot(bit);
+      same &= bit ? m : ~m;
+    }
+    const uint32_t before = (uint32_t)__popcll(same & below);
+    if (valid && before == 0) s_wcnt[wave][d] = (uint32_t)__popcll(same);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = s_base[d] + before;
+      for (int w = 0; w < wave; ++w) pos += s_wcnt[w][d];
+      key_out[pos] = k;
+      val_out[pos] = v;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < kSortThreads / 64; ++w) {
+      add += s_wcnt[w][threadIdx.x];
+      s_wcnt[w][threadIdx.x] = 0;
+    }
+    s_base[threadIdx.x] += add;
+    __syncthreads();
   }
 }
 
@@ -270,30 +354,35 @@ __global__ void k_rank_from_order(const int32_t* __restrict__ order, int32_t n, 
 }
 
 hipError_t degree_rank_scratch_bytes(int32_t n, size_t* bytes) {
-  size_t sort_bytes = 0;
-  const hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(
-      nullptr, sort_bytes, (const int32_t*)nullptr, (int32_t*)nullptr, (const int32_t*)nullptr,
-      (int32_t*)nullptr, n);
-  *bytes = 4 * sizeof(int32_t) * (size_t)n + 256 + sort_bytes;
-  return e;
+  const int64_t tiles = ((int64_t)n + kSortTile - 1) / kSortTile;
+  *bytes = 4 * sizeof(int32_t) * (size_t)n + 256 + 256 * sizeof(uint32_t) * (size_t)tiles;
+  return hipSuccess;
 }
 
 hipError_t launch_degree_rank(const GraphDev& g, int32_t* rank, void* scratch,
                               size_t scratch_bytes, hipStream_t s) {
   const int64_t n = g.n;
-  int32_t* key_in = (int32_t*)scratch;
-  int32_t* key_out = key_in + n;
-  int32_t* id_in = key_out + n;
-  int32_t* id_out = id_in + n;
+  const int64_t tiles = (n + kSortTile - 1) / kSortTile;
+  size_t need = 0;
+  (void)degree_rank_scratch_bytes(g.n, &need);
+  if (scratch_bytes < need) return hipErrorInvalidValue;
+  uint32_t* key[2] = {(uint32_t*)scratch, (uint32_t*)scratch + n};
+  int32_t* val[2] = {(int32_t*)scratch + 2 * n, (int32_t*)scratch + 3 * n};
   const size_t used = 4 * sizeof(int32_t) * (size_t)n;
-  void* sort_tmp = (char*)scratch + ((used + 255) / 256) * 256;
-  size_t sort_bytes = scratch_bytes - ((used + 255) / 256) * 256;
+  uint32_t* hist = (uint32_t*)((char*)scratch + ((used + 255) / 256) * 256);
   const int bn = (int)std::min<int64_t>((n + 255) / 256, 16384);
-  k_deg_keys<<<bn, 256, 0, s>>>(g.info, g.n, key_in, id_in);
-  hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(
-      sort_tmp, sort_bytes, key_in, key_out, id_in, id_out, (int)n, 0, 32, s);
-  if (e != hipSuccess) return e;
-  k_rank_from_order<<<bn, 256, 0, s>>>(id_out, g.n, rank);
+  k_deg_keys<<<bn, 256, 0, s>>>(g.info, g.n, g.max_deg, key[0], val[0]);
+  int passes = 1;
+  while (passes < 4 && ((uint32_t)g.max_deg >> (8 * passes)) != 0) ++passes;
+  int cur = 0;
+  for (int p = 0; p < passes; ++p) {
+    k_sort_hist<<<(unsigned)tiles, kSortThreads, 0, s>>>(key[cur], n, 8 * p, tiles, hist);
+    k_scan_u32<<<1, 1024, 0, s>>>(hist, 256 * tiles);
+    k_sort_scatter<<<(unsigned)tiles, kSortThreads, 0, s>>>(key[cur], val[cur], n, 8 * p, tiles,
+                                                            hist, key[cur ^ 1], val[cur ^ 1]);
+    cur ^= 1;
+  }
+  k_rank_from_order<<<bn, 256, 0, s>>>(val[cur], g.n, rank);
   return hipGetLastError();
 }
 

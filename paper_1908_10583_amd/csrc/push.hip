@@ -95,7 +95,7 @@ hipError_t launch_init_queries(const GraphDev& g, const Ws& w, int batch, hipStr
   return hipGetLastError();
 }
 
-// Source distributions (the paper's extension of Algorithm 1): the initial
+// Source distributions (section 6.2, the extension of Algorithm 1): the initial
 // residue is sigma (rounded to the fixed point) instead of e_s; q starts at
 // zero (the zero-filled rows). An entry outside [0, 1] is flagged.
 __global__ void k_init_dist(const double* __restrict__ sigma, const QueryDev* Q, int batch,

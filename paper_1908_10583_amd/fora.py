@@ -101,11 +101,12 @@ def _load():
         "fora_topk_workspace_size": ([P, I32, I32, ctypes.POINTER(SZ)], ctypes.c_int),
         "fora_topk_batch": ([P, I32, ctypes.POINTER(fora_query), I32, P, SZ, P, P,
                              ctypes.POINTER(fora_stats), P, P, P], ctypes.c_int),
-        "fora_push_only": ([P, I32, F64, F64, P, SZ, I32, P, P, I64,
+        "fora_push_only": ([P, I32, F64, F64, P, P, SZ, I32, P, P, I64,
                             ctypes.POINTER(fora_stats), P], ctypes.c_int),
         "fora_walk_only": ([P, I64, P, P, P, U32, U32, F64, P, SZ, ctypes.POINTER(U64), P],
                            ctypes.c_int),
         "fora_philox": ([I64, P, U32, U32, P, P], ctypes.c_int),
+        "fora_graph_rank": ([P, P, P], ctypes.c_int),
         "fora_features": ([P, I32, P, F64, F64, F64, F64, P, P], ctypes.c_int),
         "fora_mlp_forward": ([I32, P, P, P, P, P], ctypes.c_int),
         "fora_mlp_backward": ([I32, P, P, P, P, P, P, P, P, P], ctypes.c_int),
@@ -132,7 +133,7 @@ EXPORTED = ["fora_last_error", "fora_build_csr", "fora_free_graph", "fora_graph_
             "fora_workspace_size", "fora_workspace_views", "fora_ssppr", "fora_ssppr_static",
             "fora_ssppr_batch",
             "fora_dist_batch",
-            "fora_push_only", "fora_walk_only", "fora_philox", "fora_features",
+            "fora_push_only", "fora_walk_only", "fora_philox", "fora_graph_rank", "fora_features",
             "fora_mlp_forward", "fora_mlp_backward", "fora_adam_step", "fora_mlp_to_bf16",
             "fora_mlp_forward_bf16", "fora_predict_rmax", "fora_push_sweep",
             "fora_topk_workspace_size", "fora_topk_batch", "fora_build_index",
@@ -461,18 +462,25 @@ def fora_topk_batch(g: Graph, queries, kmax: int | None = None, ws: torch.Tensor
 
 def fora_push_only(g: Graph, src: int, alpha: float, rmax: float,
                    ws: torch.Tensor | None = None, max_rounds: int = 4096,
-                   log_frontiers: bool = False, frontier_cap: int | None = None, stream=None):
+                   log_frontiers: bool = False, frontier_cap: int | None = None, stream=None,
+                   sigma: torch.Tensor | None = None):
+    """The push phase alone; with ``sigma`` (float64 [n] on the device) the
+    push of that source distribution (``src`` is then not used)."""
     ws = workspace(g, 1) if ws is None else ws
+    if sigma is not None:
+        sigma = sigma.to(device=g.device, dtype=torch.float64).contiguous().view(-1)
+        if sigma.numel() != g.n:
+            raise ValueError(f"sigma must have {g.n} entries")
     sizes = np.zeros(max_rounds, np.int32)
     cap = frontier_cap if frontier_cap is not None else 64 * g.n
     flog = torch.empty(cap, dtype=torch.int32, device=g.device) if log_frontiers else None
     st = fora_stats()
-    _check(_lib.fora_push_only(g.handle, int(src), alpha, rmax, _ptr(ws), ws.numel(),
+    _check(_lib.fora_push_only(g.handle, int(src), alpha, rmax, _ptr(sigma), _ptr(ws), ws.numel(),
                                max_rounds, sizes.ctypes.data_as(ctypes.c_void_p), _ptr(flog),
                                cap if log_frontiers else 0, ctypes.byref(st),
                                ctypes.c_void_p(_stream(stream))))
     v = fora_workspace_views(g, 1, ws)
-    out = dict(r=v["residue"][0], q=v["reserve"][0], stats=st.as_dict(),
+    out = dict(r=v["residue"][0], r_fx=v["residue_fx"][0], q=v["reserve"][0], stats=st.as_dict(),
                round_sizes=sizes[:st.rounds].copy())
     if log_frontiers:
         offs = np.concatenate([[0], np.cumsum(out["round_sizes"])])
@@ -493,6 +501,13 @@ def fora_walk_only(g: Graph, plan_v, plan_omega, plan_w, key0: int, key1: int,
                                ws.numel(), ctypes.byref(steps), ctypes.c_void_p(_stream(stream))))
     v = fora_workspace_views(g, 1, ws)
     return dict(cnt=v["walk_count"][0], acc_fx=v["walk_weight_fx"][0], steps=steps.value)
+
+
+def fora_graph_rank(g: Graph, stream=None) -> torch.Tensor:
+    """The graph's degree rank (int32 [n]): out-degree descending, ties by id."""
+    out = torch.empty(g.n, dtype=torch.int32, device=g.device)
+    _check(_lib.fora_graph_rank(g.handle, _ptr(out), ctypes.c_void_p(_stream(stream))))
+    return out
 
 
 def fora_philox(ctr: np.ndarray, key, device="cuda", stream=None) -> np.ndarray:

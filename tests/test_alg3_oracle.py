@@ -1,7 +1,7 @@
-"""Pins of the oracle's Algorithm 3 parts (section 5): zero-hop pruning and
+"""Pins of the oracle's Algorithm 3 parts (section 4): zero-hop pruning and
 the push/walk balance rule. CPU only.
 
-Pruning is pinned by the decomposition pi = pi_0 + pi_1 of section 5.1: a
+Pruning is pinned by the decomposition pi = pi_0 + pi_1 of section 4.1: a
 walk that must move first ends at t with probability
 (pi(v,t) - alpha [v = t]) / (1 - alpha) (checked against the dense solve),
 its length minus one is geometric, the estimator stays unbiased and keeps the

@@ -1,5 +1,5 @@
-"""Pins of the oracle's source-distribution FORA (the paper's appendix on
-source distributions and global PageRank). CPU only.
+"""Pins of the oracle's source-distribution FORA (sections 6.2 and 6.3, the
+extension to source distributions and global PageRank). CPU only.
 
 The extension only changes Algorithm 1's start (r = sigma instead of e_s),
 so it is pinned by: the point mass sigma = e_s reducing bit for bit to the

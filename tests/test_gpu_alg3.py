@@ -1,14 +1,15 @@
 """Algorithm 3's parts on the GPU (zero-hop pruning, push/walk balance)
 against the oracle: push rounds and where the balance rule stops them, r and
-q to 1e-5, walk counts bit-exact wherever the walk plans agree, the estimate
-with the pruned walks' alpha r share, and the eps guarantee."""
+q to 1e-5, walk end-point counts and moves exactly equal to the oracle's
+pruned walks on the device's own residues, the estimate with the pruned
+walks' alpha r share, and the eps guarantee."""
 import numpy as np
 import pytest
 import scipy.stats as st
 
+import exactcmp
 import oracle
 import synth
-import walkcmp
 from oracle import exact
 
 pytestmark = pytest.mark.gpu
@@ -62,35 +63,40 @@ def _run(G, g, srcs, seeds, flags, rmax=None, walk_cost=0.0, delta=None, pf=None
     return res, rows
 
 
-def _compare(g, res, rows, i, ref, prune):
+def _compare(g, res, rows, i, ref, prune, src, seed):
     st_ = res.stats[i]
     assert st_["rounds"] == ref["rounds"]
     assert np.all(close(rows["reserve"][i], ref["q"]))
     assert np.all(close(rows["residue"][i], ref["r"]))
+    # the oracle's (pruned) walks on the plan of the device's residues
     scale = (1 - ALPHA) if prune else 1.0
-    om = walkcmp.omega(scale * rows["residue"][i].astype(np.float64), st_["omega_unit"])
-    om_ref = np.zeros(g.n)
-    om_ref[ref["plan"][0]] = ref["plan"][1]
-    d = walkcmp.check(rows["walk_count"][i].view(np.uint64), ref["cnt"], om, om_ref,
-                      rows["pi_hat"][i], ref["pi"], w_max=1.0 / st_["omega_unit"])
-    if d == 0:
-        assert st_["steps"] == ref["steps"] and st_["walks"] == ref["walks"]
+    w = exactcmp.oracle_walks_on(g, rows["residue"][i], st_["omega_unit"], int(src), int(seed),
+                                 st_["t_alpha"], scale=scale, first_move=prune)
+    assert w["walks"] == st_["walks"]
+    exactcmp.check_walks(w, rows["walk_count"][i], st_["steps"], rows["walk_weight_fx"][i])
+    # pi_hat = q + walk weights (+ alpha r for the pruned zero-hop share),
+    # formed in FP64 and rounded once
+    acc = rows["walk_weight_fx"][i].view(np.uint64).astype(np.float64) * 2.0**-62
+    p = rows["reserve"][i].astype(np.float64) + acc
+    if prune:
+        p = p + ALPHA * rows["residue"][i]
+    assert np.array_equal(rows["pi_hat"][i], p.astype(np.float32))
     order = np.lexsort((np.arange(g.n), -rows["pi_hat"][i]))[:res.ids.shape[1]]
     assert np.array_equal(res.ids[i].cpu().numpy(), order)
-    return d
+    # with the same residues the oracle's whole query gives the same plan
+    if ref["min_margin"] > 1e-5:
+        assert st_["walks"] == ref["walks"] and st_["steps"] == ref["steps"]
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_pruned_end_to_end(g1k, G1k, seed):
     res, rows = _run(G1k, g1k, [0, 17], [seed, seed + 10], PRUNE, delta=1e-3, pf=1e-3)
-    exact_plans = 0
     for i, s in enumerate((0, 17)):
         ref = oracle.fora(g1k, s, k=50, seed=seed + 10 * i, delta=1e-3, pf=1e-3, prune=True)
-        exact_plans += _compare(g1k, res, rows, i, ref, True) == 0
+        _compare(g1k, res, rows, i, ref, True, s, seed + 10 * i)
         # pruning: the plan holds (1 - alpha) of the residue mass
-        assert res.stats[i]["walks"] <= np.ceil(
-            (1 - ALPHA) * rows["residue"][i].astype(np.float64) * res.stats[i]["omega_unit"]).sum() + 1
-    assert exact_plans >= 1
+        assert res.stats[i]["walks"] == np.ceil(
+            (1 - ALPHA) * rows["residue"][i].astype(np.float64) * res.stats[i]["omega_unit"]).sum()
 
 
 def test_pruned_walks_leave_their_start(g1k, G1k):
@@ -119,7 +125,7 @@ def test_balance_rule_matches_oracle(grmat, Grmat, walk_cost):
     for i in keep:
         assert res.stats[i]["balance_stopped"] == int(refs[i]["stopped"])
         assert res.stats[i]["edge_ops"] == refs[i]["edge_ops"]
-        _compare(grmat, res, rows, i, refs[i], True)
+        _compare(grmat, res, rows, i, refs[i], True, srcs[i], i)
     assert any(refs[i]["stopped"] for i in keep)
 
 

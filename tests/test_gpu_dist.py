@@ -1,14 +1,16 @@
 """FORA for source distributions and global PageRank on the GPU against the
-oracle: push rounds, r and q to 1e-5, walk counts bit-exact wherever the walk
-plans agree, the estimate, the selection, and the eps guarantee for global
-PageRank; invalid distributions are rejected."""
+oracle: the device's push of the distribution against the oracle replaying
+its frontiers (r and q to 1e-5 element by element), walk end-point counts and
+moves exactly equal to the oracle's walks on the device's residues, the
+estimate, the selection, and the eps guarantee for global PageRank; invalid
+distributions are rejected."""
 import numpy as np
 import pytest
 import scipy.stats as st
 
+import exactcmp
 import oracle
 import synth
-import walkcmp
 from oracle import exact
 
 pytestmark = pytest.mark.gpu
@@ -54,8 +56,8 @@ def Grmat(grmat):
 
 
 def _sigma(n, seed, support):
-    # a random distribution on `support` nodes whose values are exact in FP32,
-    # so both sides start from the same residues
+    # a random distribution on `support` nodes whose values are exact in
+    # FP32, hence in the residues' fixed point: both sides start from them
     rng = np.random.default_rng(seed)
     v = rng.choice(n, support, replace=False)
     w = rng.integers(1, 1 << 10, support).astype(np.float64)
@@ -74,21 +76,34 @@ def _run(G, g, sigmas, seeds, k=50, **kw):
     return res, rows
 
 
-def _compare(g, res, rows, i, ref):
+def _compare(g, G, res, rows, i, sig, seed, ref=None):
+    """Row i against the oracle: the device's push of sigma (rerun alone
+    with its frontiers logged, equal to the row bit for bit) against the
+    oracle replaying those frontiers from sigma; walks on the device's
+    residues exactly as the oracle's (keyed by the distribution key); the
+    estimate and the selection from them. Where the oracle's own free run
+    keeps every residue clear of its threshold, it agrees as well."""
     st_ = res.stats[i]
-    assert st_["rounds"] == ref["rounds"] and st_["edge_ops"] == ref["edge_ops"]
-    assert np.all(close(rows["reserve"][i], ref["q"]))
-    assert np.all(close(rows["residue"][i], ref["r"]))
-    om = walkcmp.omega(rows["residue"][i].astype(np.float64), st_["omega_unit"])
-    om_ref = np.zeros(g.n)
-    om_ref[ref["plan"][0]] = ref["plan"][1]
-    d = walkcmp.check(rows["walk_count"][i].view(np.uint64), ref["cnt"], om, om_ref,
-                      rows["pi_hat"][i], ref["pi"], w_max=1.0 / st_["omega_unit"])
-    if d == 0:
-        assert st_["steps"] == ref["steps"] and st_["walks"] == ref["walks"]
+    p = fora.fora_push_only(G, 0, ALPHA, st_["rmax"], log_frontiers=True,
+                            sigma=torch.as_tensor(sig, device="cuda"))
+    assert np.array_equal(p["r_fx"].cpu().numpy(), rows["residue_fx"][i])
+    assert np.array_equal(p["q"].cpu().numpy(), rows["reserve"][i])
+    assert p["stats"]["rounds"] == st_["rounds"] and p["stats"]["edge_ops"] == st_["edge_ops"]
+    exactcmp.check_push(g, 0, ALPHA, st_["rmax"], p["frontiers"], rows["residue"][i],
+                        rows["reserve"][i], r0=sig)
+    w = exactcmp.oracle_walks_on(g, rows["residue"][i], st_["omega_unit"], oracle.DIST_KEY0,
+                                 seed, st_["t_alpha"])
+    assert w["walks"] == st_["walks"]
+    exactcmp.check_walks(w, rows["walk_count"][i], st_["steps"], rows["walk_weight_fx"][i])
+    acc = rows["walk_weight_fx"][i].view(np.uint64).astype(np.float64) * 2.0**-62
+    want = (rows["reserve"][i].astype(np.float64) + acc).astype(np.float32)
+    assert np.array_equal(rows["pi_hat"][i], want)
     order = np.lexsort((np.arange(g.n), -rows["pi_hat"][i]))[:res.ids.shape[1]]
     assert np.array_equal(res.ids[i].cpu().numpy(), order)
-    return d
+    if ref is not None and ref["min_margin"] > 1e-5:
+        assert st_["rounds"] == ref["rounds"] and st_["edge_ops"] == ref["edge_ops"]
+        assert np.all(close(rows["reserve"][i], ref["q"]))
+        assert st_["steps"] == ref["steps"] and st_["walks"] == ref["walks"]
 
 
 def test_distributions_match_oracle(g1k, G1k):
@@ -96,18 +111,14 @@ def test_distributions_match_oracle(g1k, G1k):
     sigmas = [_sigma(n, 1, 50), _sigma(n, 2, 3), np.where(np.arange(n) < 512, 1.0 / 512, 0.0)]
     seeds = [4, 5, 6]
     res, rows = _run(G1k, g1k, sigmas, seeds, delta=1e-3, pf=1e-3)
-    exact_plans = 0
     for i, (sg, sd) in enumerate(zip(sigmas, seeds)):
         ref = oracle.fora_dist(g1k, sg, alpha=ALPHA, k=50, seed=sd, delta=1e-3, pf=1e-3)
-        if ref["min_margin"] <= 1e-5:  # a residue within rounding of its threshold
-            continue
-        exact_plans += _compare(g1k, res, rows, i, ref) == 0
-    assert exact_plans >= 1
+        _compare(g1k, G1k, res, rows, i, sg, sd, ref)
 
 
 def test_uniform_distribution_on_rmat(grmat, Grmat):
     # global PageRank's start: every node holds 1/n (a power of two here, so
-    # exact in FP32); round 0's frontier is every node with d(v) < 1/(n r_max)
+    # exact in the residues' fixed point); round 0's frontier is every node with d(v) < 1/(n r_max)
     n = grmat.n
     sig = np.full(n, 1.0 / n)
     c = oracle.constants(grmat.m, ALPHA, 0.5, 1.0 / n, 1.0 / n)
@@ -115,11 +126,9 @@ def test_uniform_distribution_on_rmat(grmat, Grmat):
         ref = oracle.fora_dist(grmat, sig, alpha=ALPHA, k=100, seed=9, rmax=rmax,
                                log_frontiers=True)
         res, rows = _run(Grmat, grmat, [sig], [9], k=100, rmax=rmax)
-        if ref["min_margin"] <= 1e-5:
-            continue
         first = np.flatnonzero(sig > rmax * grmat.degrees())
         assert np.array_equal(np.sort(ref["frontiers"][0]), first)
-        _compare(grmat, res, rows, 0, ref)
+        _compare(grmat, Grmat, res, rows, 0, sig, 9, ref)
 
 
 def test_point_mass_pushes_like_the_single_source_query(g1k, G1k):
@@ -131,7 +140,7 @@ def test_point_mass_pushes_like_the_single_source_query(g1k, G1k):
     assert res.stats[0]["edge_ops"] == one.stats["edge_ops"]
     ref = oracle.fora(g1k, 17, k=50, seed=3, delta=1e-3, pf=1e-3,
                       walk_key=(oracle.DIST_KEY0, 3))
-    _compare(g1k, res, rows, 0, ref)
+    _compare(g1k, G1k, res, rows, 0, sig, 3, ref)
 
 
 def test_pagerank_keeps_the_guarantee(g1k, G1k):
@@ -154,7 +163,7 @@ def test_pagerank_keeps_the_guarantee(g1k, G1k):
 def test_invalid_distributions_are_rejected(g1k, G1k):
     n = g1k.n
     qs = fora.make_queries([0], k=10, n=n)
-    for bad in (-1e-3, float("nan"), float("inf")):
+    for bad in (-1e-3, float("nan"), float("inf"), 1.5):
         sig = np.full((1, n), 1.0 / n)
         sig[0, 7] = bad
         with pytest.raises(fora.FORAError) as ei:

@@ -10,17 +10,22 @@ that hold at any size:
 * every query: mass conservation, the estimate's total, the walk count as a
   function of the residues, and the selection against a stable sort of the
   estimate (computed on the device, one row at a time);
-* the oracle's push for sampled queries, among them the largest-degree
-  source of the wave;
+* the largest-degree and the median-degree source of the wave element by
+  element: the batch row's push equals the same query's push alone and the
+  oracle's replay of its frontiers (r and q to 1e-5, every push decision
+  within 1e-5 of its threshold); the median-degree query's walk end-point
+  counts and moves exactly equal to the oracle's walks on the device's
+  residues (all of its walks, in pieces over worker processes);
 * walk counts bit-exact on a sampled part of the oracle's walk plan, run on
   the full graph;
-* a query in the batch against the same query run alone."""
+* sampled queries in the batch equal to the same queries run alone, bit for
+  bit."""
 import numpy as np
 import pytest
 
+import exactcmp
 import oracle
 import synth
-import walkcmp
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
 
@@ -59,7 +64,8 @@ def refs(workload):
 @pytest.fixture(scope="module")
 def batch(workload):
     g, srcs, G, sampled = workload
-    qs = fora.make_queries(srcs, alpha=ALPHA, eps=EPS, k=K, seed=SEED, n=g.n)
+    qs = fora.make_queries(srcs, alpha=ALPHA, eps=EPS, k=K, seed=SEED, n=g.n,
+                           flags=fora.FORA_WALK_COUNTS)
     ws = fora.workspace(G, B)
     res = fora.fora_ssppr_batch(G, qs, kmax=K, ws=ws, stats=True)
     v = fora.fora_workspace_views(G, B, ws)
@@ -74,8 +80,7 @@ def batch(workload):
             pi_sum=pi.sum(dtype=torch.float64).item(),
             walks=int(torch.ceil(r.double() * omega_unit).sum().item()),
             order_ok=bool(torch.equal(order.to(torch.int32), res.ids[i]))))
-    rows = {i: {k: v[k][i].cpu().numpy().copy() for k in ("residue", "reserve", "pi_hat")}
-            for i in sampled}
+    rows = {i: exactcmp.row_of(v, i) for i in sampled}
     out = dict(stats=res.stats, per_query=per_query, rows=rows, ids=res.ids.cpu().numpy(),
                vals=res.vals.cpu().numpy())
     del v, ws, res
@@ -101,22 +106,32 @@ def test_sampled_pushes_match_oracle(workload, batch, refs):
     g, srcs, G, sampled = workload
     c, pushes = refs
     for i in sampled:
-        ref = pushes[i]
         got = batch["rows"][i]
         st_ = batch["stats"][i]
         assert st_["rmax"] == c["rmax"] and st_["omega_unit"] == c["omega_unit"]
-        r = got["residue"].astype(np.float64)
-        q = got["reserve"].astype(np.float64)
+        p = fora.fora_push_only(G, int(srcs[i]), ALPHA, c["rmax"], log_frontiers=True)
+        assert np.array_equal(p["r_fx"].cpu().numpy(), got["residue_fx"])
+        assert np.array_equal(p["q"].cpu().numpy(), got["reserve"])
+        exactcmp.check_push(g, int(srcs[i]), ALPHA, c["rmax"], p["frontiers"],
+                            got["residue"], got["reserve"])
+        del p
+        # the oracle's free-running push: the same rounds and states where no
+        # residue of it comes within 1e-5 of its threshold
+        ref = pushes[i]
         if ref["min_margin"] > 1e-5:
             assert st_["rounds"] == ref["rounds"]
-            np.testing.assert_allclose(q, ref["q"], rtol=1e-5, atol=1e-12)
-            np.testing.assert_allclose(r, ref["r"], rtol=1e-5, atol=1e-12)
-        else:
-            # a residue within FP32 rounding of its threshold may be pushed
-            # one round apart on the two sides: the states still agree closely
-            assert abs(st_["rounds"] - ref["rounds"]) <= 1
-            assert np.abs(q - ref["q"]).sum() < 1e-3
-            assert np.abs(r - ref["r"]).sum() < 1e-3
+            assert np.all(exactcmp.close(got["residue"], ref["r"]))
+
+
+def test_median_query_walks_exactly_as_the_oracle(workload, batch, refs):
+    g, srcs, G, sampled = workload
+    i = sampled[1]
+    st_ = batch["stats"][i]
+    ref = exactcmp.oracle_walks_on(g, batch["rows"][i]["residue"], st_["omega_unit"],
+                                   int(srcs[i]), SEED, st_["t_alpha"], workers=16)
+    assert ref["walks"] == st_["walks"]
+    exactcmp.check_walks(ref, batch["rows"][i]["walk_count"], st_["steps"],
+                         batch["rows"][i]["walk_weight_fx"])
 
 
 def test_sampled_walks_are_bit_exact_on_the_full_graph(workload, refs):
@@ -140,18 +155,14 @@ def test_sampled_walks_are_bit_exact_on_the_full_graph(workload, refs):
 
 def test_query_in_the_batch_equals_it_alone(workload, batch):
     g, srcs, G, sampled = workload
-    i = sampled[1]
     ws = fora.workspace(G, 1)
-    one = fora.fora_ssppr(G, int(srcs[i]), ALPHA, EPS, k=K, seed=SEED, ws=ws, stats=True)
-    v = fora.fora_workspace_views(G, 1, ws)
-    pi1 = v["pi_hat"][0].cpu().numpy().astype(np.float64)
-    pib = batch["rows"][i]["pi_hat"].astype(np.float64)
-    assert abs(one.stats["rounds"] - batch["stats"][i]["rounds"]) <= 1
-    # the same walks where the plans agree; plans differ only where FP32
-    # residues differ in rounding, which moves little mass
-    om1 = walkcmp.omega(v["residue"][0].cpu().numpy(), one.stats["omega_unit"])
-    omb = walkcmp.omega(batch["rows"][i]["residue"], one.stats["omega_unit"])
-    moved = np.abs(om1 - omb).sum()
-    assert np.abs(pi1 - pib).sum() <= 2e-3 + 2.0 * moved / one.stats["omega_unit"]
-    same = len(set(one.ids.cpu().numpy().tolist()) & set(batch["ids"][i].tolist()))
-    assert same >= int(0.98 * K)
+    for i in sampled:
+        one = fora.fora_ssppr(G, int(srcs[i]), ALPHA, EPS, k=K, seed=SEED, ws=ws, stats=True,
+                              flags=fora.FORA_WALK_COUNTS)
+        alone = exactcmp.row_of(fora.fora_workspace_views(G, 1, ws), 0)
+        for key in ("residue_fx", "reserve", "walk_count", "walk_weight_fx", "pi_hat"):
+            assert np.array_equal(alone[key], batch["rows"][i][key]), key
+        assert np.array_equal(one.ids.cpu().numpy(), batch["ids"][i])
+        assert np.array_equal(one.vals.cpu().numpy(), batch["vals"][i])
+        for key in ("rounds", "edge_ops", "walks", "steps", "r_sum"):
+            assert one.stats[key] == batch["stats"][i][key], key

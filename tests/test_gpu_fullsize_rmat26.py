@@ -1,17 +1,17 @@
 """The serving loop at the serving workload's full size: R-MAT 2^26 nodes
 (about 1.1 billion edges, 4.4 GB resident), requests with eps in {0.1, 0.5}
 and k in {50, 500} arriving together, so that they share batches on two
-slots under a memory budget. Every result equals the same query run alone:
-walk end points bit-exact wherever the two walk plans agree (and otherwise
-apart by no more than the walks the plans move), the reserve to FP32
-push-order rounding (in L1 where a residue at its threshold flips), and each
-selection is the (estimate descending, id ascending) order of its own
-estimate."""
+slots under a memory budget. Every result equals the same query run alone,
+bit for bit (residues, reserves, walk end-point counts and weights, the
+estimate and the selection), and each selection is the (estimate
+descending, id ascending) order of its own estimate. The first request's
+push (eps = 0.5) is also checked element by element against the oracle
+replaying its frontiers."""
 import numpy as np
 import pytest
 
+import exactcmp
 import synth
-import walkcmp
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
 
@@ -60,20 +60,17 @@ def test_results_alone_equal_results_in_the_mix(graph):
         v = {k: t[0].cpu().numpy() for k, t in fora.fora_workspace_views(G, 1, ws1).items()}
         ou = alone.stats["omega_unit"]
         assert r.stats["omega_unit"] == ou and r.stats["rmax"] == alone.stats["rmax"]
-        om_mix = walkcmp.omega(r.rows["residue"], ou)
-        om_alone = walkcmp.omega(v["residue"], ou)
-        d_om = walkcmp.check(r.rows["walk_count"].view(np.uint64), v["walk_count"].view(np.uint64),
-                             om_mix, om_alone, r.rows["pi_hat"], v["pi_hat"], w_max=1.0 / ou)
-        # the two pushes sum in different FP32 orders, so at this size a few
-        # residues within rounding of their threshold are pushed in one run
-        # and not the other (moving alpha r(v) into q(v)): the reserves agree
-        # in L1, and element-wise everywhere else
-        q_mix = r.rows["reserve"].astype(np.float64)
-        q_alone = v["reserve"].astype(np.float64)
-        assert np.abs(q_mix - q_alone).sum() < 1e-3
-        assert np.mean(np.abs(q_mix - q_alone) <= 1e-5 * np.abs(q_alone) + 1e-12) > 0.999
-        if d_om == 0:
-            a_vals = alone.vals.cpu().numpy()[:r.k]
-            np.testing.assert_allclose(r.vals, a_vals, rtol=2e-5, atol=1e-9)
+        for key in ("residue_fx", "reserve", "walk_count", "walk_weight_fx", "pi_hat"):
+            assert np.array_equal(r.rows[key], v[key]), key
+        assert np.array_equal(r.ids, alone.ids.cpu().numpy()[:r.k])
+        assert np.array_equal(r.vals, alone.vals.cpu().numpy()[:r.k])
+        for key in ("rounds", "edge_ops", "walks", "steps"):
+            assert r.stats[key] == alone.stats[key], key
         _is_topk(r.rows["pi_hat"], np.asarray(r.ids))
         del v
+    r = reqs[0]
+    assert r.eps == 0.5
+    p = fora.fora_push_only(G, r.src, 0.2, r.stats["rmax"], log_frontiers=True)
+    assert np.array_equal(p["r_fx"].cpu().numpy(), r.rows["residue_fx"])
+    exactcmp.check_push(g, r.src, 0.2, r.stats["rmax"], p["frontiers"], r.rows["residue"],
+                        r.rows["reserve"])

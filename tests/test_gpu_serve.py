@@ -1,11 +1,10 @@
 """The serving loop on the GPU: a Poisson trace of mixed-eps, mixed-k
 queries through several slots under a memory budget; every result equals the
-same query run alone (walks bit-exact wherever the plans agree)."""
+same query run alone, bit for bit."""
 import numpy as np
 import pytest
 
 import synth
-import walkcmp
 
 pytestmark = pytest.mark.gpu
 
@@ -38,32 +37,21 @@ def test_results_alone_equal_results_in_the_mix(graph):
     assert srv.peak <= budget and srv.max_running >= 2
     assert {r.eps for r in reqs} == {0.1, 0.5} and {r.k for r in reqs} == {50, 500}
     ws1 = fora.workspace(G, 1)
-    same_plan = 0
     for r in reqs:
         alone = fora.fora_ssppr(G, r.src, 0.2, r.eps, 1 / g.n, 1 / g.n, r.k, seed=r.seed,
                                 ws=ws1, stats=True, flags=fora.FORA_WALK_COUNTS)
         v = {k: t[0].cpu().numpy() for k, t in fora.fora_workspace_views(G, 1, ws1).items()}
-        ou = alone.stats["omega_unit"]
-        assert r.stats["omega_unit"] == ou and r.stats["rmax"] == alone.stats["rmax"]
-        om_mix = walkcmp.omega(r.rows["residue"], ou)
-        om_alone = walkcmp.omega(v["residue"], ou)
-        d_om = walkcmp.check(r.rows["walk_count"].view(np.uint64), v["walk_count"].view(np.uint64),
-                             om_mix, om_alone, r.rows["pi_hat"], v["pi_hat"], w_max=1.0 / ou)
-        np.testing.assert_allclose(r.rows["reserve"], v["reserve"], rtol=1e-5, atol=1e-12)
-        if d_om == 0:
-            # same walks; the reserve agrees to FP32 push-order rounding, so the
-            # top-k agrees up to that rounding and to swaps of near-ties
-            same_plan += 1
-            a_ids = alone.ids.cpu().numpy()[:r.k]
-            a_vals = alone.vals.cpu().numpy()[:r.k]
-            np.testing.assert_allclose(r.vals, a_vals, rtol=2e-5, atol=1e-9)
-            gap = np.abs(np.diff(np.concatenate([[np.inf], a_vals, [-np.inf]])))
-            clear = (gap[:-1] > 4e-5 * a_vals) & (gap[1:] > 4e-5 * a_vals)
-            assert np.array_equal(r.ids[clear], a_ids[clear])
+        assert r.stats["omega_unit"] == alone.stats["omega_unit"]
+        assert r.stats["rmax"] == alone.stats["rmax"]
+        for key in ("residue_fx", "reserve", "walk_count", "walk_weight_fx", "pi_hat"):
+            assert np.array_equal(r.rows[key], v[key]), key
+        assert np.array_equal(r.ids, alone.ids.cpu().numpy()[:r.k])
+        assert np.array_equal(r.vals, alone.vals.cpu().numpy()[:r.k])
+        for key in ("rounds", "edge_ops", "walks", "steps"):
+            assert r.stats[key] == alone.stats[key], key
         # the top-k is the order of the query's own estimate
         order = np.lexsort((np.arange(g.n), -r.rows["pi_hat"]))[:r.k]
         assert np.array_equal(r.ids, order)
-    assert same_plan >= len(reqs) - 2
     dup = [r for r in reqs if r.id in (3, 24)]
     assert dup[0].rows is not None and dup[1].rows is not None
 

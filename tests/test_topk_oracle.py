@@ -1,4 +1,4 @@
-"""Pins of the oracle's top-k FORA (Algorithm 5, section 6.2). CPU only.
+"""Pins of the oracle's top-k FORA (Algorithm 5, section 5.2). CPU only.
 
 Definition 2 is checked against the exact PPR of a dense solve over many
 seeds (the frequency of violations must stay within the failure budget),
@@ -34,7 +34,7 @@ def test_delta_sequence():
 
 
 def test_iterations_hold_the_union_bound(g1k):
-    # Algorithm 5's guarantee (section 6.2) is a union bound: each iteration
+    # Algorithm 5's guarantee (section 5.2) is a union bound: each iteration
     # keeps every node with pi >= delta within eps/2 of its PPR except with
     # probability p_f / (n log2(n/k)), so that over the n nodes and the
     # log2(n/k) halvings of delta the failure probability is p_f. Lemma 2's
