@@ -307,7 +307,9 @@ __device__ __forceinline__ void push_edge(int b, int u, u64 inc, double rmax, u6
 // (piece of a high-in-degree node, pull group). A chunk item scans the
 // chunk's in-degrees, finds each in-edge's owner, and reads the source's
 // increment unit once; each pulling member of the group sums its own
-// increment into its LDS row.
+// increment into its LDS row. The nodes that cross their thresholds are
+// appended to the next frontier with one reservation per chunk item (a
+// block scan of the per-node crossing counts), not through a queue.
 template <int G>
 __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
     int t, Ctrl* ctrl, u64* __restrict__ fr_out, u64 cap, u64* __restrict__ r,
@@ -319,17 +321,12 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
   __shared__ u64 s_pre[kScatterBlock];
   __shared__ int32_t s_start[kScatterBlock];
   __shared__ u64 s_sum[G][kScatterBlock];
-  __shared__ u64 s_queue[kQueueCap];
-  __shared__ unsigned s_qn;
-  __shared__ u64 s_qbase;
   __shared__ u64 s_tmp[kScatterBlock / 64];
   __shared__ u64 s_tmpu[kScatterBlock / 64];
-  (void)t;
+  __shared__ u64 s_base;
   const int ngroups = ctrl->npull;
   if (ngroups == 0) return;  // uniform
-  const NextQueue nq{s_queue, &s_qn, &s_qbase, &ctrl->fr_cnt[(t + 1) & 1], fr_out, cap, ctrl};
-  if (threadIdx.x == 0) s_qn = 0;
-  __syncthreads();
+  u64* out_cnt = &ctrl->fr_cnt[(t + 1) & 1];
   const u64 chunks = ((u64)n + kScatterBlock - 1) / kScatterBlock;
   const u64 chunk_items = chunks * (u64)ngroups;
   const u64 items = chunk_items + inhub_pieces * (u64)ngroups;
@@ -395,6 +392,9 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
         flush(lo);
       }
       __syncthreads();
+      // bit g: member g's residue at u is now over its threshold (u was not
+      // in this round's frontier, so this is its only crossing)
+      unsigned cross = 0u;
       if (u < n) {
         const int d_u = info[u].y;
         for (int g = 0; g < G; ++g) {
@@ -404,8 +404,21 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
             const size_t gi = (size_t)b * n + u;
             const u64 now = r[gi] + add;
             r[gi] = now;
-            if (now > fx_threshold(Q[b].rmax, d_u)) nq.push(((u64)b << 32) | (uint32_t)u);
+            if (now > fx_threshold(Q[b].rmax, d_u)) cross |= 1u << g;
           }
+        }
+      }
+      // the chunk's next-frontier entries: one reservation for the block
+      u64 tot;
+      u64 pos = block_exclusive_scan((u64)__popc(cross), s_tmp, tot);
+      if (tot != 0ull) {  // uniform
+        if (threadIdx.x == 0) s_base = atomicAdd(out_cnt, tot);
+        __syncthreads();
+        pos += s_base;
+        for (unsigned m = cross; m != 0u; m &= m - 1u, ++pos) {
+          const int b = grp * G + __ffs(m) - 1;
+          if (pos < cap) fr_out[pos] = ((u64)b << 32) | (uint32_t)u;
+          else atomicOr(&ctrl->error, kErrFrontierOverflow);
         }
       }
     } else {
@@ -442,17 +455,16 @@ __global__ __launch_bounds__(kScatterBlock) void k_push_pull(
           const u64 old = atomicAdd(&r[gi], sums[g]);
           const u64 now = old + sums[g];
           const u64 thr = fx_threshold(Q[b].rmax, d_u);
-          if (old <= thr && now > thr) nq.push(((u64)b << 32) | (uint32_t)u);
+          if (old <= thr && now > thr) {
+            const u64 pos = atomicAdd(out_cnt, 1ull);
+            if (pos < cap) fr_out[pos] = ((u64)b << 32) | (uint32_t)u;
+            else atomicOr(&ctrl->error, kErrFrontierOverflow);
+          }
         }
       }
     }
-    // flush when the LDS queue is half full (decision taken after a barrier,
-    // so it is the same for the whole block)
-    __syncthreads();
-    const bool full = s_qn > kQueueCap / 2;
-    if (full) nq.flush();
+    __syncthreads();  // LDS rows are rewritten by the next item
   }
-  nq.flush();
 }
 
 __global__ __launch_bounds__(kScatterBlock) void k_push_scatter(

@@ -250,11 +250,14 @@ def sources_uniform(g: Graph, count: int, seed: int, exclude=None) -> np.ndarray
     return np.sort(rng.choice(pool, size=count, replace=False)).astype(np.int32)
 
 
-def sources_by_degree(g: Graph, count: int, seed: int) -> np.ndarray:
+def sources_by_degree(g: Graph, count: int, seed: int, exclude=None) -> np.ndarray:
     """``count`` sources drawn with replacement, probability proportional to
-    out-degree (duplicates kept, in draw order)."""
+    out-degree (duplicates kept, in draw order); nodes in ``exclude`` are
+    never drawn."""
     rng = np.random.Generator(np.random.PCG64(seed))
     deg = g.degrees().astype(np.float64)
+    if exclude is not None:
+        deg[np.asarray(exclude, np.int64)] = 0.0
     return rng.choice(g.n, size=count, replace=True, p=deg / deg.sum()).astype(np.int32)
 
 
@@ -307,6 +310,14 @@ def workload(name: str) -> tuple[Graph, np.ndarray]:
         # the multithreaded sampler builds this graph in seconds (numpy: a minute)
         g = rmat_graph(23, seed=23, sampler="c")
         return g, sources_by_degree(g, 1024, seed=2323)
+    if name == "rmat23L":
+        # training sources for a learned r_max on the rmat23 graph (drawn the
+        # same way, never one of the 1,024 workload sources), then those
+        # 1,024 (held out)
+        g = rmat_graph(23, seed=23, sampler="c")
+        bench = sources_by_degree(g, 1024, seed=2323)
+        train = sources_by_degree(g, 4096, seed=2324, exclude=np.unique(bench))
+        return g, np.concatenate([train, bench])
     if name == "rmat22":
         g = rmat_graph(22, seed=22)
         return g, sources_uniform(g, 22048, seed=2222)

@@ -115,8 +115,10 @@ def test_device_pushes_a_node_the_oracle_leaves_and_the_replay_reconciles(pull_r
         ref = oracle.push(g, 0, ALPHA, rmax, log_frontiers=True)
         # round 0: s; round 1: v1 and v2 (and no one else has residue yet)
         assert list(got["frontiers"][1]) == [1, 2] and list(ref["frontiers"][1]) == [1, 2]
-        # round 2: u on the device, not in the oracle's free run
-        assert 3 in got["frontiers"][2] and 3 not in ref["frontiers"][2]
+        # round 2: u on the device, not in the oracle's free run (which may
+        # end after round 1)
+        ref_f2 = ref["frontiers"][2] if len(ref["frontiers"]) > 2 else []
+        assert len(got["frontiers"]) > 2 and 3 in got["frontiers"][2] and 3 not in ref_f2
         exactcmp.check_push(g, 0, ALPHA, rmax, got["frontiers"], got["r"].cpu().numpy(),
                             got["q"].cpu().numpy())
         G.close()
