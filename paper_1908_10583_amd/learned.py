@@ -51,7 +51,7 @@ def sweep(G, srcs, alpha=0.2, eps=0.5, delta=None, pf=None, batch=128, log=None)
         e, w = fora.fora_push_sweep(G, qs, MULTS, ws=ws)
         E[i:i + len(part)] = e
         W[i:i + len(part)] = w
-        if log and (i // batch) % 8 == 0:
+        if log and (i // batch) % 2 == 0:
             log(f"sweep {i + len(part)}/{len(srcs)} ({time.perf_counter() - t0:.1f}s)")
     return E, W
 
