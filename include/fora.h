@@ -118,7 +118,10 @@ typedef struct fora_query {
 #define FORA_MAX_BATCH 4096
 
 /* Dense per-query arrays inside a workspace, for inspection. Query b's row
- * starts at b*n. Valid after a call on that workspace has completed. */
+ * starts at b*n. Valid after a call on that workspace has completed; the
+ * three walk-phase rows (walk_count, walk_weight_fx, pi_hat) share memory
+ * with the push's frontier arrays, so after fora_push_only or
+ * fora_push_sweep they hold no meaning (fora_walk_only leaves pi_hat so). */
 typedef struct fora_views {
   uint64_t *residue_fx;       /* r(s, v), unsigned fixed point with 62
                                  fraction bits [batch][n]                     */
@@ -181,7 +184,9 @@ int fora_graph_info(const fora_graph *g, int32_t *n, int64_t *m,
 int fora_get_tuning(const fora_graph *g, fora_tuning *out);
 int fora_set_tuning(fora_graph *g, const fora_tuning *t);
 
-/* Bytes of workspace for `batch` concurrent queries (1..FORA_MAX_BATCH). */
+/* Bytes of workspace for `batch` concurrent queries (1..FORA_MAX_BATCH):
+ * about 52 bytes per node and query (residue 8, reserve 4, and 40 that the
+ * push's frontier arrays and the walk phase's plan and sums take in turn). */
 int fora_workspace_size(const fora_graph *g, int32_t batch, size_t *bytes);
 int fora_workspace_views(const fora_graph *g, int32_t batch, void *d_ws,
                          fora_views *views);
@@ -221,7 +226,7 @@ int fora_ssppr(const fora_graph *g, int32_t src, double alpha, double eps,
  * up on the first call on each device. Results equal fora_ssppr's bit for
  * bit. FORA_E_NOMEM if the graph needs more workspace than the array holds
  * (fora_workspace_size(g, 1) > FORA_STATIC_SCRATCH_BYTES: graphs up to
- * about 1.4 million nodes fit); other errors as fora_ssppr. */
+ * about 2.5 million nodes fit); other errors as fora_ssppr. */
 #define FORA_STATIC_SCRATCH_BYTES (128u << 20)
 int fora_ssppr_static(const fora_graph *g, int32_t src, double alpha, double eps, double delta,
                       double pf, int32_t k, double opt_rmax, uint64_t seed, int32_t *d_topk_ids,

@@ -454,34 +454,10 @@ Layout make_layout(const GraphDev& g, int32_t batch) {
   L.tiles_per_row = (n + kPlanTile - 1) / kPlanTile;
   L.plan_tiles = L.tiles_per_row * batch;
   L.topk_blocks = (n + kTopkTile - 1) / kTopkTile;
-  // region cleared at the start of every call
-  L.ctrl = take(sizeof(Ctrl));
-  L.zero_begin = L.ctrl;
-  L.qstats = take(sizeof(StatSlot) * (size_t)kStatSlots * batch);
-  L.r = take(8 * cap);
-  L.q = take(4 * cap);
-  L.cnt = take(8 * cap);
-  L.acc = take(8 * cap);
-  L.hist = take(4 * (size_t)kHistBins * batch);
-  L.cand_cnt = take(4 * (size_t)batch);
-  const size_t pg = (size_t)pull_group_for(batch);
-  L.incd = take(8 * (((size_t)batch + pg - 1) / pg * pg) * (size_t)n);  // whole pull groups
-  L.ecnt = take(8 * 2 * (size_t)kStatSlots * batch);
-  L.stop = take(4 * (size_t)batch);
-  L.zero_end = align_up(off, 256);
-  L.mode = take(4 * (size_t)batch);
-  L.pull_list = take(4 * (size_t)batch);
   // written before being read
   L.queries = take(sizeof(QueryDev) * batch);
-  L.pi = take(4 * cap);
-  L.fr0 = take(8 * cap);
-  L.fr1 = take(8 * cap);
-  L.frx = take(8 * cap);
-  L.hub_idx = take(8 * (size_t)L.hub_cap);
-  L.hub_base = take(8 * (size_t)L.hub_cap);
-  L.plan_gi = take(8 * cap);
-  L.plan_off = take(8 * (cap + 1));
-  L.plan_wfx = take(8 * cap);
+  L.mode = take(4 * (size_t)batch);
+  L.pull_list = take(4 * (size_t)batch);
   L.tile_cnt = take(4 * (size_t)L.plan_tiles);
   L.tile_walks = take(8 * (size_t)L.plan_tiles);
   L.tile_eoff = take(8 * (size_t)L.plan_tiles);
@@ -490,6 +466,38 @@ Layout make_layout(const GraphDev& g, int32_t batch) {
   L.cand_key = take(4 * (size_t)FORA_MAX_K * batch);
   L.cand_id = take(4 * (size_t)FORA_MAX_K * batch);
   L.blk_ties = take(4 * (size_t)L.topk_blocks * batch);
+  // cleared at the start of every call, up to and including incd
+  L.ctrl = take(sizeof(Ctrl));
+  L.zero_begin = L.ctrl;
+  L.qstats = take(sizeof(StatSlot) * (size_t)kStatSlots * batch);
+  L.r = take(8 * cap);
+  L.q = take(4 * cap);
+  L.hist = take(4 * (size_t)kHistBins * batch);
+  L.cand_cnt = take(4 * (size_t)batch);
+  L.ecnt = take(8 * 2 * (size_t)kStatSlots * batch);
+  L.stop = take(4 * (size_t)batch);
+  // Phase region: the push's arrays and the walk phase's arrays are never
+  // live at once, so they share it (8 B x 4 against 8 B x 5 per node and
+  // query). The walk view's sums are cleared by the plan, after the push.
+  const size_t phase = align_up(off, 256);
+  const size_t pg = (size_t)pull_group_for(batch);
+  L.incd = take(8 * (((size_t)batch + pg - 1) / pg * pg) * (size_t)n);  // whole pull groups
+  L.zero_end = align_up(off, 256);
+  L.fr0 = take(8 * cap);
+  L.fr1 = take(8 * cap);
+  L.frx = take(8 * cap);
+  L.hub_idx = take(8 * (size_t)L.hub_cap);
+  L.hub_base = take(8 * (size_t)L.hub_cap);
+  const size_t push_end = off;
+  off = phase;
+  L.acc = take(8 * cap);
+  L.cnt = take(8 * cap);
+  L.plan_gi = take(8 * cap);
+  L.plan_off = take(8 * (cap + 1));
+  L.plan_wfx = take(8 * cap);
+  // the estimate is formed after the walks, when the plan is no longer read
+  L.pi = L.plan_gi;
+  off = std::max(off, push_end);
   L.total = align_up(off, 256);
   return L;
 }
@@ -1232,6 +1240,7 @@ int fora_walk_only(const fora_graph* gc, int64_t entries, const int32_t* d_v,
   FORA_HIP(hipSetDevice(g->device));
   FORA_HIP(launch_fill_zero((char*)d_ws + c.L.zero_begin, c.L.zero_end - c.L.zero_begin, s));
   FORA_HIP(hipMemcpyAsync(c.w.queries, &qd, sizeof(qd), hipMemcpyHostToDevice, s));
+  FORA_HIP(launch_clear_walk_sums(c.w, c.L, s));
   if (entries > 0) {
     FORA_HIP(launch_walk_plan_from_host(g->dev, c.w, entries, d_v, d_omega, d_w, s));
     FORA_HIP(launch_walks(g->dev, c.w, walk_blocks(g), call_chunk(g, c),

@@ -247,6 +247,7 @@ constexpr uint32_t kDistKey0 = 0xFFFFFFFFu;  // first walk key word of a source 
 hipError_t launch_push_round(const GraphDev& g, const Ws& w, const Layout& L, int batch,
                              int t, int blocks, int pull_ratio, int32_t* frontier_log,
                              int64_t log_cap, hipStream_t s);
+hipError_t launch_clear_walk_sums(const Ws& w, const Layout& L, hipStream_t s);
 hipError_t launch_plan(const GraphDev& g, const Ws& w, const Layout& L, int batch,
                        hipStream_t s);
 hipError_t launch_walks(const GraphDev& g, const Ws& w, int blocks, int chunk, bool agg,

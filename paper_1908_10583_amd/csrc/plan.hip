@@ -7,6 +7,8 @@
 // r'(v) = (1 - alpha) r(v) instead. Also collects r_sum per query (an exact
 // integer sum of the fixed-point residues) and counts residues left above
 // r_max * d(v) (must be zero after the push).
+#include <algorithm>
+
 #include "internal.h"
 #include "scan.h"
 
@@ -151,8 +153,30 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_write(
   }
 }
 
+// The walk phase's end-point sums share memory with the push's frontier
+// arrays, so they are cleared once the push is over (a kernel, so that it can
+// sit in a captured graph; skipped while the push still runs there).
+__global__ __launch_bounds__(256) void k_clear_walk_sums(const Ctrl* ctrl, u64* __restrict__ acc,
+                                                         u64* __restrict__ cnt, u64 cap) {
+  if (ctrl->skip) return;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += stride) {
+    acc[i] = 0ull;
+    cnt[i] = 0ull;
+  }
+}
+
+hipError_t launch_clear_walk_sums(const Ws& w, const Layout& L, hipStream_t s) {
+  const u64 cap = (u64)L.cap;
+  const u64 blocks = std::min<u64>((cap + 255) / 256, 8192);
+  k_clear_walk_sums<<<(unsigned)std::max<u64>(blocks, 1), 256, 0, s>>>(w.ctrl, w.acc, w.cnt, cap);
+  return hipGetLastError();
+}
+
 hipError_t launch_plan(const GraphDev& g, const Ws& w, const Layout& L, int batch,
                        hipStream_t s) {
+  const hipError_t e = launch_clear_walk_sums(w, L, s);
+  if (e != hipSuccess) return e;
   dim3 grid((unsigned)L.tiles_per_row, (unsigned)batch);
   k_plan_count<<<grid, kPlanThreads, 0, s>>>(w.r, w.queries, w.qstats, g.info, g.n,
                                              (int)L.tiles_per_row, w.tile_cnt, w.tile_walks,

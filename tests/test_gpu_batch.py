@@ -131,6 +131,26 @@ def test_graph_with_too_few_rounds_finishes_on_host(g1k, G1k):
         assert [s["rounds"] for s in res.stats] == [s["rounds"] for s in eager.stats]
 
 
+def test_shared_phase_memory_leaves_no_trace(g1k, G1k):
+    # the push's frontier arrays and the walk phase's plan and sums share one
+    # region of the workspace: a workspace filled with junk and then used by
+    # push-only and walk-only calls gives the rows of a fresh one, and a
+    # walk-only call with no plan entries leaves all-zero sums
+    ws0 = fora.workspace(G1k, 1)
+    base = fora.fora_ssppr(G1k, 7, k=50, seed=3, ws=ws0, stats=True, flags=WC)
+    ref = _rows(G1k, 1, ws0)
+    ws = fora.workspace(G1k, 1)
+    ws.fill_(0xA5)
+    fora.fora_push_only(G1k, 11, 0.2, 1e-6, ws=ws)
+    w = fora.fora_walk_only(G1k, [], [], [], 1, 2, 0.2, ws=ws)
+    assert w["steps"] == 0
+    assert not w["cnt"].any().item() and not w["acc_fx"].any().item()
+    fora.fora_push_only(G1k, 11, 0.2, 1e-6, ws=ws)
+    res = fora.fora_ssppr(G1k, 7, k=50, seed=3, ws=ws, stats=True, flags=WC)
+    _same_query(_rows(G1k, 1, ws), ref, 0, 0)
+    assert torch.equal(res.ids, base.ids) and torch.equal(res.vals, base.vals)
+
+
 def test_mixed_parameters_match_single_calls(g1k, G1k):
     srcs = [5, 5, 900, 64]
     eps = [0.5, 0.3, 0.5, 0.2]

@@ -43,7 +43,7 @@ def test_static_entry_point_equals_fora_ssppr_twice_second_smaller():
 
 
 def test_static_entry_point_rejects_graphs_beyond_its_array():
-    n = 2_000_000  # a cycle: about 96 bytes of workspace per node > 128 MiB
+    n = 3_000_000  # a cycle: about 52 bytes of workspace per node > 128 MiB
     rowptr = np.arange(n + 1, dtype=np.int32)
     colidx = ((np.arange(n) + 1) % n).astype(np.int32)
     G = fora.Graph.from_numpy(rowptr, colidx)
