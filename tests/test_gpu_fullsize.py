@@ -155,3 +155,35 @@ def test_query_in_the_batch_equals_it_alone(workload, batch, i):
     assert np.array_equal(one.vals.cpu().numpy(), batch["vals"][i])
     for key in ("rounds", "edge_ops", "walks", "steps", "r_sum"):
         assert one.stats[key] == batch["stats"][i][key], key
+
+
+@pytest.mark.parametrize("shape", [
+    # push rounds only (no pulls), the host-driven loop, small grids
+    dict(pull_ratio=0, graph_rounds=0, push_blocks_per_cu=2, walk_blocks_per_cu=2,
+         walk_chunk=64),
+    # a pull in nearly every round, a graph too short for the push
+    dict(pull_ratio=1 << 20, graph_rounds=5, push_blocks_per_cu=8, walk_agg=1),
+])
+def test_rows_do_not_depend_on_the_launch_configuration(workload, batch, shape):
+    # residue sums are integers and walks are keyed by (v, j, step), so push
+    # against pull rounds, grid sizes, graph capture and end-point
+    # aggregation change no bit of a query's rows
+    g, srcs, G = workload
+    i = SAMPLED[0]
+    G.set_tuning(**shape)
+    try:
+        ws = fora.workspace(G, 1)
+        one = fora.fora_ssppr(G, int(srcs[i]), ALPHA, EPS, k=K, seed=SEED, ws=ws, stats=True,
+                              flags=fora.FORA_WALK_COUNTS)
+        row = exactcmp.row_of(fora.fora_workspace_views(G, 1, ws), 0)
+    finally:
+        G.set_tuning(**BENCH_TUNING)
+    if shape["pull_ratio"] == 0:
+        assert one.stats["pull_rounds"] == 0
+    else:
+        assert one.stats["pull_rounds"] >= one.stats["rounds"] // 2
+    for key in ("residue_fx", "reserve", "walk_count", "walk_weight_fx", "pi_hat"):
+        assert np.array_equal(row[key], batch["rows"][i][key]), key
+    assert np.array_equal(one.ids.cpu().numpy(), batch["ids"][i])
+    for key in ("rounds", "edge_ops", "walks", "steps", "r_sum"):
+        assert one.stats[key] == batch["stats"][i][key], key
