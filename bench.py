@@ -272,8 +272,15 @@ def main():
                     unit="GB/s", frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
                     traffic_source=traffic_src, kernel="k_walks", bytes_per_launch=alg_bytes,
                     avg_launch_ms=round(walk_s * 1e3, 3))
+    if traffic is not None:
+        # the counters' HBM bytes per launch over this run's launch time: the
+        # hardware rate, beside the algorithmic one above
+        roofline["traffic_gbs"] = round(traffic / walk_s / 1e9, 1)
+        roofline["traffic_frac"] = round(traffic / walk_s / 1e9 / PEAK_HBM_GBS, 4)
     log(f"headline: {steps_per_s:.3e} walk-steps/s, {qps:.2f} q/s; walk kernel "
-        f"{achieved:.0f} GB/s algorithmic ({achieved / PEAK_HBM_GBS:.1%})")
+        f"{achieved:.0f} GB/s algorithmic ({achieved / PEAK_HBM_GBS:.1%})"
+        + (f", {roofline['traffic_gbs']:.0f} GB/s by the counters "
+           f"({roofline['traffic_frac']:.1%})" if traffic is not None else ""))
 
     def timed_leg(fn, steps):
         for i in range(leg_warmup):
