@@ -134,6 +134,53 @@ def cpu_baseline(g, srcs, alpha, eps, seed, walk_budget=3_000_000):
                         f"per host core at once"))
 
 
+def small_graph_leg(alpha, eps, k, seed, cache, args, log):
+    """One query at a time on R-MAT 2^20 (16.6M edges, 100 sources uniform
+    over nodes with out-degree >= 1): queries/s and latency in the launch
+    shape tuned for one query, then per-phase latency from the eager path's
+    events. The graph fits in the 256 MB Infinity Cache, so this leg makes
+    no HBM-roofline claim."""
+    import torch
+    import synth
+    from paper_1908_10583_amd import autotune, fora
+
+    g2, srcs2 = synth.workload("rmat20")
+    G2 = fora.Graph.from_numpy(g2.rowptr, g2.colidx, device="cuda:0")
+    tun = None
+    if not args.no_autotune:
+        one = fora.make_queries(srcs2[:1], alpha=alpha, eps=eps, k=k, seed=seed, n=g2.n)
+        tun = dict(autotune.autotune(G2, one, path=cache, force=args.retune)["tuning"])
+    ws1 = fora.workspace(G2, 1)
+    o1 = (torch.empty(k, dtype=torch.int32, device="cuda:0"),
+          torch.empty(k, dtype=torch.float32, device="cuda:0"))
+    for s in srcs2[:2]:
+        fora.fora_ssppr(G2, int(s), alpha, eps, k=k, seed=seed, ws=ws1, out=o1)
+    torch.cuda.synchronize()
+    lat, steps = [], 0
+    t1 = time.perf_counter()
+    for s in srcs2:
+        ts = time.perf_counter()
+        r = fora.fora_ssppr(G2, int(s), alpha, eps, k=k, seed=seed, ws=ws1, out=o1, stats=True)
+        lat.append(time.perf_counter() - ts)
+        steps += r.stats["steps"]
+    dt = time.perf_counter() - t1
+    G2.set_tuning(graph_rounds=0)
+    ph = dict(ms_push=0.0, ms_plan=0.0, ms_walk=0.0, ms_topk=0.0)
+    for s in srcs2:
+        r = fora.fora_ssppr(G2, int(s), alpha, eps, k=k, seed=seed, ws=ws1, out=o1, stats=True)
+        for key in ph:
+            ph[key] += r.stats[key] / len(srcs2)
+    out = dict(workload=f"{g2.name}: n={g2.n} m={g2.m}, {len(srcs2)} sources one at a time",
+               queries_per_s=round(len(srcs2) / dt, 2), walk_steps_per_s=steps / dt,
+               latency_ms_p50=round(float(np.median(lat)) * 1e3, 3),
+               latency_ms_p99=round(float(np.percentile(lat, 99)) * 1e3, 3),
+               eager_phases_ms={key: round(v, 3) for key, v in ph.items()}, tuning=tun)
+    log(f"single queries on R-MAT 2^20: {out['queries_per_s']} q/s, p50 "
+        f"{out['latency_ms_p50']} ms")
+    G2.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +206,8 @@ def main():
     ap.add_argument("--no-topk", action="store_true", help="skip the top-k FORA leg")
     ap.add_argument("--no-pagerank", action="store_true", help="skip the global PageRank leg")
     ap.add_argument("--no-index", action="store_true", help="skip the FORA+ (index) leg")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the single-query leg on R-MAT 2^20 (100 sources)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy, whose HBM counter "
                          "readings calibrate FETCH_SIZE / WRITE_SIZE")
@@ -448,6 +497,10 @@ def main():
         del ws1
         G.set_tuning(**saved_tuning)
 
+    small = None
+    if not args.no_small:
+        small = small_graph_leg(alpha, eps, k, seed, cache, args, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, bounded sample)...")
@@ -474,6 +527,7 @@ def main():
         "global_pagerank": pagerank_leg,
         "fora_plus_index": index_leg,
         "graph_replay": graph_mode,
+        "single_query_rmat20": small,
         "tuning": tuning,
         "phases_ms_per_step": {p: round(v / args.steps, 3) for p, v in ph_sum.items()},
         "per_step": {"walks": per_launch_walks, "walk_steps": per_launch_steps,
