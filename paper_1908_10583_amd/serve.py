@@ -13,10 +13,10 @@ so requests that arrive while others are on the GPU are admitted as soon as
 a slot and memory free up, and their device work overlaps.
 
 Each query's result depends only on (graph, source, alpha, eps, delta, p_f,
-k, r_max, seed): walks are keyed by (source, seed, start node, walk index),
-so a query returns the same walks alone or in any batch wherever its push
-left the same plan (the push sums in FP32 in an order that can differ
-between batches, which can move a walk count omega_v by one).
+k, r_max, seed): the push sums residues in fixed point (integer sums, the
+same in any order) and walks are keyed by (source, seed, start node, walk
+index), so a query returns the same result, bit for bit, alone or in any
+batch.
 """
 from __future__ import annotations
 
