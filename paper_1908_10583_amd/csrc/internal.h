@@ -6,16 +6,19 @@
 //   queries   QueryDev[batch]: per-query constants computed on the host
 //   r         uint64[batch][n]  residue, unsigned fixed point (62 fraction bits)
 //   q         float[batch][n]   reserve (FP32)
-//   cnt       uint64[batch][n]  walk end-point counts
-//   acc       uint64[batch][n]  walk weights, fixed point (62 fraction bits)
-//   pi        float[batch][n]   q + acc, the estimate
-//   fr0/fr1   uint64[batch*n]   frontier entries (query << 32 | node)
-//   frx       uint64[batch*n]   per-frontier-entry increment (1-alpha) x / d (fixed point)
-//   plan_*    walk plan: entry (query << 32 | node), walk offset, weight
+//   then one region that the push and the walk phase take in turn:
+//   push:  incd      dense increments for pull rounds, [groups][n][G]
+//          fr0/fr1   uint64[batch*n]   frontier entries (query << 32 | node)
+//          frx       uint64[batch*n]   per-entry increment (1-alpha) x / d (fixed point)
+//   walks: acc       uint64[batch][n]  walk weights, fixed point (62 fraction bits)
+//          cnt       uint64[batch][n]  walk end-point counts
+//          plan_*    walk plan: entry (query << 32 | node), walk offset, weight
+//          pi        float[batch][n]   q + acc, the estimate (over plan_gi, after the walks)
 //   tiles     per-tile counts and offsets for the plan scan
 //   topk      histograms, selection state and candidates
-// Graph: rowptr/colidx borrowed from the caller, plus an owned int2 table
-// info[v] = {rowptr[v], d(v)} so that a walk step reads one 8-byte record.
+// Graph: rowptr/colidx borrowed from the caller, plus owned tables: info[v]
+// = {rowptr[v], d(v)}, the degree rank, the reverse CSR, and the walk records
+// (a walk step reads one 8-byte slot of the current node's record).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -240,7 +243,7 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_graph_check(const GraphDev& g, int* d_flags, int* d_maxdeg, int* d_hubs,
                               int2* info, hipStream_t s);
 hipError_t launch_init_queries(const GraphDev& g, const Ws& w, int batch, hipStream_t s);
-// r = sigma (double[batch][n], rounded to FP32), then the round-0 frontier
+// r = sigma (double[batch][n], rounded to the fixed point), then the round-0 frontier
 hipError_t launch_init_dist(const GraphDev& g, const Ws& w, const Layout& L, int batch,
                             const double* sigma, hipStream_t s);
 constexpr uint32_t kDistKey0 = 0xFFFFFFFFu;  // first walk key word of a source distribution
