@@ -20,7 +20,8 @@
 //   Entries of degree <= kHubDeg are expanded per block (256 entries, degrees
 //   scanned in LDS); larger ones are cut into kHubPiece-edge pieces that any
 //   block may take.
-// * pull (dense rounds, frontier edges * kPullRatio > n + m): every node sums
+// * pull (dense rounds, frontier edges * pull_ratio > n + m, pull_ratio from
+//   the tuning, kPullRatio by default): every node sums
 //   the dense increments of its in-neighbours over the reverse graph (LDS
 //   accumulation, no atomics to HBM), then updates r(u) once and tests it.
 //   The dense increments sit at each node's degree rank (GraphDev::rank),
