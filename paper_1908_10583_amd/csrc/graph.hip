@@ -1,5 +1,8 @@
-// Graph ingest checks, the per-node {row start, out-degree} table, a zero
-// fill, and the device Philox block kernel used for RNG checks.
+// Graph ingest: the CSR checks, the per-node {row start, out-degree} table,
+// the reverse CSR for pull rounds (its in-lists' order follows an atomic
+// cursor and does not matter: pull sums are integers), the degree rank (a
+// stable LSD radix sort), the walk records, and the FORA+ index plan; also
+// a zero fill and the Philox block kernel used for RNG checks.
 #include "internal.h"
 #include "scan.h"
 
