@@ -39,8 +39,8 @@ PEAK_HBM_GBS = 8000.0
 # no per-node walk counts, so no count update is charged.
 BYTES_PER_STEP = 12
 BYTES_PER_WALK = 16
-# queries per batched call by workload (dense per-query state: about 90 bytes
-# per node and query, so 256 queries of 2^23 nodes take ~190 GB of HBM)
+# queries per batched call by workload (dense per-query state: about 52 bytes
+# per node and query, so 256 queries of 2^23 nodes take ~112 GB of HBM)
 DEFAULT_WAVE = {"rmat23": 256}
 # launch shapes the library's autotuner chose on MI355X for these workloads
 TUNING_CACHE = os.path.join(ROOT, "paper_1908_10583_amd", "tuning_mi355x.json")
@@ -50,21 +50,34 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def code_digest(paths) -> str:
+    """SHA-256 of the sources' code (paths relative to the repository):
+    comments removed and whitespace runs collapsed, so that a comment edit
+    keeps a counter record valid and any change to the code does not."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for src in paths:
+        text = open(os.path.join(ROOT, src)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
+        h.update(b"\0")
+    return h.hexdigest()
+
+
 def recorded_traffic(kernel: str, tag: str):
     """HBM-side bytes per launch from the committed counter record for this
     workload (tag: workload and batch, e.g. rmat23_b256), or None if there is
-    none or the kernel's sources changed since the counters were taken."""
+    none or the kernel's code changed since the counters were taken."""
     import glob
-    import hashlib
     for path in glob.glob(os.path.join(ROOT, "profiles", f"{kernel}_{tag}_traffic.json")):
         rec = json.load(open(path))
-        h = hashlib.sha256()
         try:
-            for src in rec["sources"]:
-                h.update(open(os.path.join(ROOT, src), "rb").read())
+            digest = code_digest(rec["sources"])
         except OSError:
             continue
-        if h.hexdigest() == rec["source_sha256"]:
+        if digest == rec.get("code_sha256"):
             return rec["traffic_bytes_per_launch"], os.path.relpath(path, ROOT)
     return None, None
 

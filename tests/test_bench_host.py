@@ -1,8 +1,7 @@
 """The benchmark's host logic (CPU only): it refuses more than one GPU with a
 one-line JSON message, and it takes HBM traffic from a committed counter
-record only while the kernel's sources are the ones the counters were taken
-on."""
-import hashlib
+record only while the kernel's code is the code the counters were taken on
+(comments do not count)."""
 import json
 import os
 import shutil
@@ -24,27 +23,41 @@ def test_more_than_one_gpu_is_refused():
     assert len(lines) == 1 and "error" in json.loads(lines[0])
 
 
-def _tree(tmp_path, text):
+V1 = "// the kernel\nint f(int x) {\n  return x + 1;  /* one */\n}\n"
+
+
+def _tree(tmp_path, monkeypatch, text):
+    """A one-source tree whose counter record was taken on V1."""
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     src = tmp_path / "k.hip"
-    src.write_text(text)
+    src.write_text(V1)
     (tmp_path / "profiles").mkdir()
     rec = dict(sources=["k.hip"], traffic_bytes_per_launch=1234,
-               source_sha256=hashlib.sha256(b"kernel v1").hexdigest())
+               code_sha256=bench.code_digest(["k.hip"]))
     (tmp_path / "profiles" / "k_walks_w_b1_traffic.json").write_text(json.dumps(rec))
+    src.write_text(text)
     return src
 
 
-def test_traffic_record_is_used_while_the_sources_match(tmp_path, monkeypatch):
-    _tree(tmp_path, "kernel v1")
-    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+def test_traffic_record_is_used_while_the_code_matches(tmp_path, monkeypatch):
+    _tree(tmp_path, monkeypatch, V1)
     assert bench.recorded_traffic("k_walks", "w_b1") == (
         1234, os.path.join("profiles", "k_walks_w_b1_traffic.json"))
     assert bench.recorded_traffic("k_walks", "other_b1") == (None, None)
 
 
-def test_traffic_record_is_dropped_once_a_source_changes(tmp_path, monkeypatch):
-    src = _tree(tmp_path, "kernel v2")
-    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+def test_comment_and_layout_edits_keep_the_record(tmp_path, monkeypatch):
+    _tree(tmp_path, monkeypatch,
+          "// the kernel, reworded\n/* a new\n   block comment */\nint f(int x)\n{\n"
+          "    return x + 1;\n}\n")
+    assert bench.recorded_traffic("k_walks", "w_b1")[0] == 1234
+
+
+@pytest.mark.parametrize("code", ["int f(int x) { return x + 2; }",
+                                  "int f(int x) { return x - 1; }",
+                                  "int f(long x) { return x + 1; }"])
+def test_traffic_record_is_dropped_once_the_code_changes(tmp_path, monkeypatch, code):
+    src = _tree(tmp_path, monkeypatch, code)
     assert bench.recorded_traffic("k_walks", "w_b1") == (None, None)
     src.unlink()  # a missing source counts as changed
     assert bench.recorded_traffic("k_walks", "w_b1") == (None, None)
@@ -55,7 +68,7 @@ def test_traffic_record_is_dropped_once_a_source_changes(tmp_path, monkeypatch):
 def test_committed_traffic_records_are_well_formed(path):
     rec = json.load(open(os.path.join(ROOT, "profiles", path)))
     assert rec["traffic_bytes_per_launch"] > 0
-    assert len(rec["source_sha256"]) == 64
+    assert len(rec["code_sha256"]) == 64
     for src in rec["sources"]:
         assert os.path.exists(os.path.join(ROOT, src)), src
 
