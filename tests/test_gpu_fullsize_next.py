@@ -1,0 +1,146 @@
+"""The next rows at the single-query workload's full size (R-MAT 2^20 nodes,
+16.6M edges), element by element against the oracle:
+
+* Algorithm 3, zero-hop pruning with the balance rule (section 4): the
+  balanced push is the first R rounds of the plain push at the same r_max
+  (the rule only stops it), so the oracle replays the plain push's logged
+  frontiers (all of them: every decision within 1e-5 of its threshold;
+  the first R: r and q element by element), evaluates the rule at every
+  round boundary from the replayed state (it must hold first at R, unless
+  it is within rounding of its bound there), and walks the plan of the
+  device's residues with the forced first move: counts and moves exact;
+* FORA+ (section 3.3): the walk-destination index bit for bit against the
+  oracle's, then an index query whose plan reaches beyond the index (the
+  tail runs live with the index key), its end points exactly the oracle's;
+* global PageRank (section 6.3, sigma = 1/n): the device's push of the
+  uniform start through the replay, its walks exact under the distribution
+  key, the estimate and the selection from them."""
+import numpy as np
+import pytest
+
+import exactcmp
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1908_10583_amd import fora  # noqa: E402
+
+ALPHA = 0.2
+WORKERS = 16
+KEY = (424242, 7)
+WC = fora.FORA_WALK_COUNTS
+
+
+@pytest.fixture(scope="module")
+def workload():
+    g, srcs = synth.workload("rmat20")
+    G = fora.Graph.from_numpy(g.rowptr, g.colidx)
+    yield g, srcs, G
+    G.close()
+
+
+def _row(G, ws, B=1, i=0):
+    return exactcmp.row_of(fora.fora_workspace_views(G, B, ws), i)
+
+
+@pytest.mark.parametrize("i,share", [(0, 0.5), (37, 0.25)])
+def test_algorithm3_element_wise(workload, i, share):
+    g, srcs, G = workload
+    s, n = int(srcs[i]), g.n
+    c = oracle.constants(g.m, ALPHA, 0.5, 1.0 / n, 1.0 / n)
+    rmax = c["rmax"] / 32
+    # the plain push at this r_max, alone, with its frontiers; all of it
+    # through the replay
+    p = fora.fora_push_only(G, s, ALPHA, rmax, log_frontiers=True)
+    exactcmp.check_push(g, s, ALPHA, rmax, p["frontiers"], p["r"].cpu().numpy(),
+                        p["q"].cpu().numpy())
+    total_ops = p["stats"]["edge_ops"]
+    # a walk cost at which the rule ends the push about `share` of the way
+    wc = share * total_ops / ((1 - ALPHA) * c["omega_unit"])
+    qs = fora.make_queries([s], k=500, seed=i, n=n, rmax=rmax, walk_cost=wc,
+                           flags=fora.FORA_PRUNE_ZERO_HOP | fora.FORA_BALANCE | WC)
+    ws = fora.workspace(G, 1)
+    res = fora.fora_ssppr_batch(G, qs, ws=ws, stats=True)
+    st = res.stats[0]
+    row = _row(G, ws)
+    R = st["rounds"]
+    assert st["balance_stopped"] == 1 and 0 < R < p["stats"]["rounds"]
+    # the balanced push is the plain push's first R rounds
+    rep = oracle.push_replay(g, s, ALPHA, rmax, p["frontiers"][:R])
+    assert rep["max_listed_shortfall"] <= exactcmp.TAU
+    assert np.all(exactcmp.close(row["residue"], rep["r"]))
+    assert np.all(exactcmp.close(row["reserve"], rep["q"]))
+    ops = np.cumsum([int(g.degrees()[F].sum()) for F in p["frontiers"][:R]])
+    assert st["edge_ops"] == int(ops[-1])
+    # the rule, checked after every round from the replayed state: first
+    # met after round R (pushed mass = reserve / alpha)
+    for t in range(R):
+        q_t = oracle.push_replay(g, s, ALPHA, rmax, p["frontiers"][:t + 1])["q"]
+        est = (1 - ALPHA * q_t.sum() / ALPHA) * (1 - ALPHA) * st["omega_unit"] * wc
+        met = ops[t] >= est
+        tie = abs(ops[t] - est) <= 1e-9 * est
+        assert met == (t == R - 1) or tie, (t, ops[t], est)
+    # pruned walks on the device's residues: plan of (1 - alpha) r, each walk
+    # starting with a forced move
+    w = exactcmp.oracle_walks_on(g, row["residue"], st["omega_unit"], s, i, st["t_alpha"],
+                                 scale=1 - ALPHA, first_move=True, workers=WORKERS)
+    assert w["walks"] == st["walks"]
+    exactcmp.check_walks(w, row["walk_count"], st["steps"], row["walk_weight_fx"])
+    acc = row["walk_weight_fx"].view(np.uint64).astype(np.float64) * 2.0**-62
+    est_pi = row["reserve"].astype(np.float64) + acc + ALPHA * row["residue"]
+    assert np.array_equal(row["pi_hat"], est_pi.astype(np.float32))
+    order = np.lexsort((np.arange(n), -row["pi_hat"]))[:500]
+    assert np.array_equal(res.ids[0].cpu().numpy(), order)
+
+
+def test_index_and_index_query_at_full_size(workload):
+    g, srcs, G = workload
+    wpd = 0.5
+    fora.fora_build_index(G, ALPHA, wpd, *KEY)
+    ref = oracle.build_index(g, ALPHA, wpd, KEY)
+    off, dest = fora.fora_index_export(G)
+    assert np.array_equal(off.cpu().numpy().view(np.uint64), ref["off"])
+    assert np.array_equal(dest.cpu().numpy(), ref["dest"])
+    del off, dest, ref
+    s = int(srcs[5])
+    qs = fora.make_queries([s], k=500, seed=0, n=g.n, flags=fora.FORA_USE_INDEX | WC)
+    ws = fora.workspace(G, 1)
+    res = fora.fora_ssppr_batch(G, qs, ws=ws, stats=True)
+    st = res.stats[0]
+    # the plan asks for up to r_max* omega_unit (about 3) walks per degree,
+    # the index holds 0.5: most walks read it, the rest run live
+    assert 0 < st["steps"]
+    exactcmp.check_query(g, G, s, ALPHA, st["rmax"], _row(G, ws), st, key0=KEY[0],
+                         key1=KEY[1], workers=WORKERS, steps=False)
+
+
+def test_global_pagerank_at_full_size(workload):
+    g, srcs, G = workload
+    n = g.n
+    sig = np.full(n, 1.0 / n)  # 2^-20: exact in the residues' fixed point
+    qs = fora.make_queries([0], k=500, seed=9, n=n, flags=WC)
+    ws = fora.workspace(G, 1)
+    sig_d = torch.as_tensor(sig, dtype=torch.float64, device="cuda").view(1, n)
+    res = fora.fora_dist_batch(G, qs, sig_d, ws=ws, stats=True)
+    st = res.stats[0]
+    row = _row(G, ws)
+    p = fora.fora_push_only(G, 0, ALPHA, st["rmax"], log_frontiers=True, sigma=sig_d.view(-1))
+    assert np.array_equal(p["r_fx"].cpu().numpy(), row["residue_fx"])
+    assert np.array_equal(p["q"].cpu().numpy(), row["reserve"])
+    exactcmp.check_push(g, 0, ALPHA, st["rmax"], p["frontiers"], row["residue"],
+                        row["reserve"], r0=sig)
+    del p
+    w = exactcmp.oracle_walks_on(g, row["residue"], st["omega_unit"], oracle.DIST_KEY0, 9,
+                                 st["t_alpha"], workers=WORKERS)
+    assert w["walks"] == st["walks"]
+    exactcmp.check_walks(w, row["walk_count"], st["steps"], row["walk_weight_fx"])
+    acc = row["walk_weight_fx"].view(np.uint64).astype(np.float64) * 2.0**-62
+    assert np.array_equal(row["pi_hat"],
+                          (row["reserve"].astype(np.float64) + acc).astype(np.float32))
+    order = np.lexsort((np.arange(n), -row["pi_hat"]))[:500]
+    assert np.array_equal(res.ids[0].cpu().numpy(), order)
