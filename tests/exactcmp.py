@@ -129,3 +129,29 @@ def check_query(g, G, s, alpha, rmax, row, stats, key0=None, key1=0, workers=1, 
     check_walks(ref, row["walk_count"], stats["steps"] if steps else None,
                 row["walk_weight_fx"])
     return rep, ref
+
+
+def check_topk_iterations(g, G, s, alpha, k, seed, iters, delta, ids, vals, eps=0.5,
+                          workers=1):
+    """Top-k FORA (Algorithm 5) of source s took `iters` iterations and ended
+    at `delta` with result (ids, vals): reruns each iteration as a plain query
+    (eps / 2, p_f / (n log2(n / k)), that iteration's delta, seed + iteration)
+    and checks it against the oracle (check_query), the stopping rule on its
+    k-th estimate, and that the result is the last iteration's bit for bit."""
+    from paper_1908_10583_amd import fora
+    n = g.n
+    pf_it = (1.0 / n) / (n * max(np.log2(n / k), 1.0))
+    deltas = oracle.topk_deltas(n, k)
+    assert delta == deltas[iters - 1]
+    ws = fora.workspace(G, 1)
+    for it in range(iters):
+        one = fora.fora_ssppr(G, s, alpha, eps / 2, deltas[it], pf_it, k, seed=seed + it, ws=ws,
+                              stats=True, flags=fora.FORA_WALK_COUNTS)
+        row = row_of(fora.fora_workspace_views(G, 1, ws), 0)
+        check_query(g, G, s, alpha, one.stats["rmax"], row, one.stats, key1=seed + it,
+                    workers=workers)
+        kth = float(one.vals[k - 1].cpu())
+        stop = kth >= (1 + eps) * deltas[it] or it == len(deltas) - 1
+        assert stop == (it == iters - 1), (it, kth, deltas[it])
+    assert np.array_equal(one.ids.cpu().numpy(), ids[:k])
+    assert np.array_equal(one.vals.cpu().numpy(), vals[:k])

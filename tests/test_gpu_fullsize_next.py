@@ -12,6 +12,10 @@
 * FORA+ (section 3.3): the walk-destination index bit for bit against the
   oracle's, then an index query whose plan reaches beyond the index (the
   tail runs live with the index key), its end points exactly the oracle's;
+* top-k FORA (Algorithm 5, section 5.2) for k = 500 and k = 50: every
+  iteration rerun as a plain query and checked like the whole queries
+  above, the stopping rule on its k-th estimate, the result the last
+  iteration's bit for bit;
 * global PageRank (section 6.3, sigma = 1/n): the device's push of the
   uniform start through the replay, its walks exact under the distribution
   key, the estimate and the selection from them."""
@@ -144,3 +148,15 @@ def test_global_pagerank_at_full_size(workload):
                           (row["reserve"].astype(np.float64) + acc).astype(np.float32))
     order = np.lexsort((np.arange(n), -row["pi_hat"]))[:500]
     assert np.array_equal(res.ids[0].cpu().numpy(), order)
+
+
+@pytest.mark.parametrize("i,k", [(0, 500), (37, 50)])
+def test_topk_fora_at_full_size(workload, i, k):
+    g, srcs, G = workload
+    s = int(srcs[i])
+    qs = fora.make_queries([s], k=k, seed=3, n=g.n)
+    res, iters, delta = fora.fora_topk_batch(G, qs, stats=True)
+    assert iters[0] >= 2  # at least one iteration did not stop
+    exactcmp.check_topk_iterations(g, G, s, ALPHA, k, 3, int(iters[0]), float(delta[0]),
+                                   res.ids[0].cpu().numpy(), res.vals[0].cpu().numpy(),
+                                   workers=WORKERS)

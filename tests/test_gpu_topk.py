@@ -54,23 +54,7 @@ def _same_topk(ids, vals, ref, omega_unit):
 
 
 def _iterations_on_their_own(g, G, s, k, seed, iters, delta, ids, vals, eps=0.5):
-    """Reruns each iteration the device ran as a plain query and checks it
-    against the oracle, the stopping rule on its estimate, and the result."""
-    n = g.n
-    pf_it = (1.0 / n) / (n * max(np.log2(n / k), 1.0))
-    deltas = oracle.topk_deltas(n, k)
-    assert delta == deltas[iters - 1]
-    ws = fora.workspace(G, 1)
-    for it in range(iters):
-        one = fora.fora_ssppr(G, s, ALPHA, eps / 2, deltas[it], pf_it, k, seed=seed + it, ws=ws,
-                              stats=True, flags=fora.FORA_WALK_COUNTS)
-        row = exactcmp.row_of(fora.fora_workspace_views(G, 1, ws), 0)
-        exactcmp.check_query(g, G, s, ALPHA, one.stats["rmax"], row, one.stats, key1=seed + it)
-        kth = float(one.vals[k - 1].cpu())
-        stop = kth >= (1 + eps) * deltas[it] or it == len(deltas) - 1
-        assert stop == (it == iters - 1), (it, kth, deltas[it])
-    assert np.array_equal(one.ids.cpu().numpy(), ids[:k])
-    assert np.array_equal(one.vals.cpu().numpy(), vals[:k])
+    exactcmp.check_topk_iterations(g, G, s, ALPHA, k, seed, iters, delta, ids, vals, eps=eps)
 
 
 @pytest.mark.parametrize("k", [5, 50])
