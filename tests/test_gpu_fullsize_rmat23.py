@@ -19,7 +19,14 @@ that hold at any size:
 * walk counts bit-exact on a sampled part of the oracle's walk plan, run on
   the full graph;
 * sampled queries in the batch equal to the same queries run alone, bit for
-  bit."""
+  bit;
+* the learned r_max (the committed model for this workload, trained on
+  other degree-weighted sources): FORA at the predicted thresholds of 64
+  sources of the wave in one batch keeps the per-query invariants, and the
+  query with the median prediction goes element by element through the
+  replay with its walks exact on the device's residues."""
+import os
+
 import numpy as np
 import pytest
 
@@ -33,9 +40,10 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
-from paper_1908_10583_amd import fora  # noqa: E402
+from paper_1908_10583_amd import fora, learned  # noqa: E402
 
 ALPHA, EPS, K, SEED, B = 0.2, 0.5, 500, 0, 256
+MODEL = os.path.join(os.path.dirname(learned.__file__), "models", "rmat23_rmax_mlp.json")
 # the launch shape the autotuner picks for 256-query waves of this workload
 WAVE_TUNING = dict(walk_blocks_per_cu=16, walk_chunk=1024, push_blocks_per_cu=32,
                    graph_rounds=0, pull_ratio=64, record_ids=1, walk_agg=0)
@@ -166,3 +174,36 @@ def test_query_in_the_batch_equals_it_alone(workload, batch):
         assert np.array_equal(one.vals.cpu().numpy(), batch["vals"][i])
         for key in ("rounds", "edge_ops", "walks", "steps", "r_sum"):
             assert one.stats[key] == batch["stats"][i][key], key
+
+
+def test_learned_rmax_at_the_batched_workload(workload):
+    g, srcs, G, _ = workload
+    model = learned.Model.load(MODEL)
+    sub = srcs[:64]
+    rm, fb = model.predict_rmax(G, sub, ALPHA, EPS)
+    rm = rm.cpu().numpy()
+    rstar = oracle.constants(g.m, ALPHA, EPS, 1.0 / g.n, 1.0 / g.n)["rmax"]
+    assert fb == 0 and np.all(rm < rstar)  # the model lowers r_max for every source
+    Bl = len(sub)
+    qs = fora.make_queries(sub, alpha=ALPHA, eps=EPS, k=K, seed=SEED, n=g.n, rmax=rm,
+                           flags=fora.FORA_WALK_COUNTS)
+    ws = fora.workspace(G, Bl)
+    res = fora.fora_ssppr_batch(G, qs, kmax=K, ws=ws, stats=True)
+    v = fora.fora_workspace_views(G, Bl, ws)
+    for i in range(Bl):
+        st_ = res.stats[i]
+        r, q, pi = v["residue"][i], v["reserve"][i], v["pi_hat"][i]
+        assert st_["rmax"] == rm[i] and st_["term_violations"] == 0
+        assert abs(r.sum(dtype=torch.float64).item() + q.sum(dtype=torch.float64).item()
+                   - 1.0) < 1e-4
+        assert abs(pi.sum(dtype=torch.float64).item() - 1.0) < 1e-4
+        assert st_["walks"] == int(torch.ceil(r.double() * st_["omega_unit"]).sum().item())
+        order = torch.argsort(-pi, stable=True)[:K].to(torch.int32)
+        assert torch.equal(order, res.ids[i])
+    i = int(np.argsort(rm)[Bl // 2])
+    row = exactcmp.row_of(v, i)
+    st_ = res.stats[i]
+    del v, ws
+    torch.cuda.empty_cache()
+    exactcmp.check_query(g, G, int(sub[i]), ALPHA, float(rm[i]), row, st_, key1=SEED,
+                         workers=16)
