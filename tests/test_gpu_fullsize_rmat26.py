@@ -6,11 +6,15 @@ bit for bit (residues, reserves, walk end-point counts and weights, the
 estimate and the selection), and each selection is the (estimate
 descending, id ascending) order of its own estimate. The first request's
 push (eps = 0.5) is also checked element by element against the oracle
-replaying its frontiers."""
+replaying its frontiers, and a sampled part of its walk plan is walked on
+the device and by the oracle: the walk records hold no ids at this size
+(the end node's id comes from its header), and the end-point counts and
+moves must be equal."""
 import numpy as np
 import pytest
 
 import exactcmp
+import oracle
 import synth
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
@@ -74,3 +78,13 @@ def test_results_alone_equal_results_in_the_mix(graph):
     assert np.array_equal(p["r_fx"].cpu().numpy(), r.rows["residue_fx"])
     exactcmp.check_push(g, r.src, 0.2, r.stats["rmax"], p["frontiers"], r.rows["residue"],
                         r.rows["reserve"])
+    del p
+    pv, po, pw = oracle.plan(r.rows["residue"], r.stats["omega_unit"])
+    assert int(po.sum()) == r.stats["walks"]
+    rng = np.random.default_rng(26)
+    pick = np.union1d(rng.choice(len(pv), min(2000, len(pv)), replace=False),
+                      np.argsort(po)[-3:])
+    pv, po, pw = pv[pick], po[pick], pw[pick]
+    ref = oracle.walks(g, r.src, r.seed, r.stats["t_alpha"], pv, po, pw)
+    got = fora.fora_walk_only(G, pv, po, pw, r.src, r.seed, 0.2)
+    exactcmp.check_walks(ref, got["cnt"].cpu().numpy(), got["steps"], got["acc_fx"].cpu().numpy())
